@@ -1,0 +1,208 @@
+"""Benchmark of the fused BGK collide-and-stream step on one MI355X.
+
+Default workload: D3Q19 BGK Taylor-Green vortex, 256^3 fully periodic, FP32
+populations, u0 = 0.05, tau = 0.8.  A "step" is one lattice time step (one
+launch of the fused kernel over every cell).  Prints ONE JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload tgv3d|channel|cavity]
+                    [--storage f32|f16|bf16|f64] [--shifted 0|1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & HBM GB/s (% peak), D3Q19 BGK 256³; FP16-store vs FP32 at stated error"
+HBM_PEAK_GBS = 8000.0
+STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="tgv3d", choices=["tgv3d", "channel", "cavity"])
+    ap.add_argument("--storage", default=None, choices=[None, "f64", "f32", "f16", "bf16"])
+    ap.add_argument("--shifted", type=int, default=None)
+    ap.add_argument("--n", type=int, default=256, help="tgv3d edge length")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="wall-clock budget of the oracle CPU baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def make_workload(args):
+    from paper_2307_11752_amd import workloads as W
+
+    if args.workload == "tgv3d":
+        wl = W.tgv3d(n=args.n, u0=0.05, tau=0.8, steps=1000, storage="f32")
+        shifted = False
+        desc = (f"tgv3d: D3Q19 BGK Taylor-Green vortex {args.n}^3 fully periodic, u0=0.05, "
+                "tau=0.8")
+    elif args.workload == "channel":
+        wl = W.channel_spheres()
+        shifted = True
+        desc = ("channel: D3Q19 BGK 512x128x128, periodic x, bounce-back walls + random spheres "
+                "r 4-10 (~20% solid, seed 2307), Guo g=1e-6, tau=0.7")
+    else:
+        wl = W.cavity2d(64)
+        shifted = False
+        desc = ("cavity2d: D2Q9 BGK lid-driven cavity 64x64, tau=0.6, lid 0.05, "
+                "halfway bounce-back + moving wall")
+    storage = args.storage or wl.storage
+    if args.shifted is not None:
+        shifted = bool(args.shifted)
+    return wl, storage, shifted, desc
+
+
+def cpu_baseline(wl, budget_s, u0):
+    """Time the FP64 oracle on the same lattice for a bounded number of steps."""
+    import numpy as np
+
+    import oracle
+
+    oracle.build(force=False)
+    ref = oracle.Lattice(wl.descriptor, wl.material, wl.periodic, wl.tau, g=wl.g,
+                         u_wall=wl.u_wall)
+    ref.init_equilibrium(None, None if u0 is None else u0[: (3 if wl.descriptor else 2)])
+    nfluid = int(np.count_nonzero(wl.material == 1))
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        ref.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 1000:
+            break
+    cores = oracle.num_threads()
+    return ref, steps, el, nfluid, cores
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md, 'More than one GPU'); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2307_11752_amd as P
+
+    wl, storage, shifted, desc = make_workload(args)
+    nx, ny, nz = wl.shape
+    N = nx * ny * nz
+    q = 9 if wl.descriptor == 0 else 19
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    lat = P.Lattice(wl.descriptor, wl.shape, wl.tau, storage=storage, shifted=shifted,
+                    stream=stream)
+    lat.set_geometry(wl.material, wl.periodic)
+    lat.set_body_force(wl.g)
+    lat.set_wall_velocity(wl.u_wall)
+    _, nfluid = lat.info()
+    masked = nfluid != N
+
+    # --- oracle CPU baseline (rank 0, N=1), and a full-size parity sample ---
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        ref, csteps, cel, cfluid, cores = cpu_baseline(wl, args.cpu_seconds, wl.u0)
+        cpu = {"value": round(N * csteps / cel / 1e6, 3), "unit": "MLUPS", "cores": cores,
+               "kind": "oracle",
+               "sample": f"{csteps} steps of the full {nx}x{ny}x{nz} lattice (FP64 oracle, "
+                         f"{cel:.1f} s wall, OpenMP over z-planes)"}
+        lat.init_equilibrium(None, wl.u0)
+        lat.step(csteps)
+        rho_g, u_g = (t.cpu().numpy() for t in lat.moments())
+        rho_o, u_o = ref.moments()
+        fl = wl.material == 1
+        du = u_g[:, fl] - u_o[:, fl]
+        parity = {"steps": csteps,
+                  "u_rel_l2": float(np.linalg.norm(du) / max(np.linalg.norm(u_o[:, fl]), 1e-300)),
+                  "u_max_abs": float(np.max(np.abs(du))),
+                  "rho_max_abs": float(np.max(np.abs(rho_g[fl] - rho_o[fl])))}
+        del ref
+
+    # --- GPU timing ---
+    lat.init_equilibrium(None, wl.u0)
+    m0, _, _ = lat.totals()
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    lat.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = ev0.elapsed_time(ev1) / max(args.steps, 1)
+    m1, j1, stats = lat.totals()
+
+    ms_per_step = wall * 1e3 / max(args.steps, 1)
+    mlups = N * args.steps / wall / 1e6
+    mlups_fluid = nfluid * args.steps / wall / 1e6
+    sb = STORE_BYTES[storage]
+    alg_bytes = nfluid * 2 * q * sb + (N if masked else 0)
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+
+    extra = {}
+    if args.workload == "tgv3d":
+        # kinetic-energy decay against exp(-2 nu |k|^2 t), nu = (tau - 1/2)/3
+        rho, u = lat.moments()
+        ke = float(0.5 * torch.sum(rho * torch.sum(u * u, dim=0)).item())
+        u0 = torch.as_tensor(wl.u0)
+        ke0 = float(0.5 * torch.sum(u0 * u0).item())
+        k2 = 3 * (2 * math.pi / nx) ** 2
+        nu = (wl.tau - 0.5) / 3
+        t = args.warmup + args.steps
+        extra["ke_ratio_over_closed_form"] = ke / ke0 / math.exp(-2 * nu * k2 * t)
+        extra["ke_time_steps"] = t
+    extra["mass_drift_rel"] = (m1 - m0) / m0
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if storage == "f64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "shape": [nx, ny, nz], "cells": N, "fluid_cells": nfluid,
+                   "storage": storage + ("-shifted" if shifted else ""), "tau": wl.tau,
+                   "propagation": "AA in place"},
+        "mlups_fluid": round(mlups_fluid, 2),
+        "kernel_ms_per_step": round(kernel_ms, 5),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "kernel": f"step_kernel<Q={q},{storage}{',shifted' if shifted else ''}>"},
+        "cpu_baseline": cpu,
+        "oracle_parity": parity,
+        "checks": extra,
+        "paper_context": {"value": 17.2699, "unit": "MLUPs",
+                          "what": "guide console log, bstep2d D2Q9, unstated hardware/precision"},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) lattice Boltzmann hot path: fused BGK
+ * collide-and-stream on D2Q9 / D3Q19 lattices with halfway bounce-back walls,
+ * moving-wall bounce-back, periodic wrap and Guo body-force forcing.
+ *
+ * Method: OpenLB User Guide, release 1.6 (arXiv:2307.11752).
+ *   - collide and stream:      Introduction, section "Lattice Boltzmann Methods"
+ *                              (collision equation, BGK operator, streaming equation)
+ *   - BGK collision:           Core Concepts, "Collision Operators" (BGK listing)
+ *   - descriptors:             Core Concepts, "Descriptor" (D2Q9 listing; D3Q19 figure)
+ *   - Guo forcing:             Simulation Models, "Coupling Between Momentum and
+ *                              Energy Equations" (velocity shift and forcing equations)
+ *   - material numbers:        Geometry Creation, "Setting Material Numbers"
+ *   - bounce-back dynamics:    Initial and Boundary Conditions, "Additional Options"
+ *   - equilibrium initialisation: Initial and Boundary Conditions,
+ *                              "Define Initial Conditions"
+ *   - lattice statistics:      lesson "Extract Data From a Simulation"
+ * All quantities are in lattice units (dx = dt = 1, c_s^2 = 1/3).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  * Every call returns an lbm_status (0 = LBM_OK, negative = error).  No call
+ *    throws or aborts; on error the handle keeps its previous state and
+ *    lbm_last_error() describes the failure.
+ *  * Cell index idx = x + nx*(y + ny*z), x fastest; N = nx*ny*nz.  D2Q9 needs nz == 1.
+ *  * Device buffers are caller-owned (e.g. PyTorch tensors) and must outlive the
+ *    handle.  The library never allocates device memory.
+ *  * Work is enqueued on the stream given at creation (NULL = the null stream).
+ *    Calls marked "async" return before the device finishes; calls marked
+ *    "sync" wait for that stream.
+ *  * A handle is not thread-safe; distinct handles are independent.
+ *
+ * Velocity ordering (needed only to read raw population buffers): D2Q9 follows
+ * the guide's listing {(0,0),(-1,1),(-1,0),(-1,-1),(0,-1),(1,-1),(1,0),(1,1),(0,1)}.
+ * D3Q19 is ordered as rest, then (-1,0,0),(0,-1,0),(0,0,-1),(-1,-1,0),(-1,1,0),
+ * (-1,0,-1),(-1,0,1),(0,-1,-1),(0,-1,1), then the negatives of entries 1..9 in
+ * the same order, so opposite(i) = i + 9 for 1 <= i <= 9 (the D2Q9 listing's
+ * convention, with 4 in place of 9).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_lattice lbm_lattice; /* opaque handle */
+
+typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 } lbm_descriptor;
+
+/* Population storage type.  F64 storage computes in double; every other type
+ * is converted to float in registers and computes in float. */
+typedef enum {
+  LBM_STORE_F64 = 0,
+  LBM_STORE_F32 = 1,
+  LBM_STORE_F16 = 2,  /* IEEE binary16 */
+  LBM_STORE_BF16 = 3  /* bfloat16 */
+} lbm_storage;
+
+/* Creation flags. */
+#define LBM_FLAG_SHIFTED 1u /* store f_i - w_i instead of f_i (any storage type) */
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_ARG = -1,         /* bad argument: size, pointer, tau <= 1/2, NaN input */
+  LBM_ERR_GEOMETRY = -2,    /* material layout rejected (see lbm_set_geometry) */
+  LBM_ERR_UNSUPPORTED = -3, /* material 4/5/>5, lattice too large */
+  LBM_ERR_HIP = -4,         /* a HIP runtime call failed; text in lbm_last_error */
+  LBM_ERR_STATE = -5,       /* call order violated (e.g. step before geometry/init) */
+  LBM_ERR_NONFINITE = -6    /* NaN/Inf found in a reduction */
+} lbm_status;
+
+/* Sizes of the two caller-allocated device buffers for a lattice.
+ * pop_bytes: q*N populations of the storage type (structure of arrays,
+ * population i of cell idx at element i*N + idx).  aux_bytes: per-cell link
+ * masks plus reduction scratch.  Host-only; needs no GPU. */
+lbm_status lbm_required_bytes(lbm_descriptor d, int nx, int ny, int nz, lbm_storage s,
+                              size_t* pop_bytes, size_t* aux_bytes);
+
+/* Create a lattice on the current HIP device.  tau is the BGK relaxation time
+ * (omega = 1/tau, collision equation of the guide's introduction); it must be
+ * > 1/2 (the guide requires a relaxation time greater than 0.5), or +INFINITY
+ * for omega = 0 (pure streaming, used for bit-exact tests).  dev_pop/dev_aux
+ * must hold at least lbm_required_bytes() and be 256-byte aligned.  hip_stream
+ * is a hipStream_t (NULL = null stream).  The lattice starts with no geometry,
+ * g = 0 and u_w = 0.  Host-side argument checks run before any HIP call. */
+lbm_status lbm_lattice_create(lbm_lattice** out, lbm_descriptor d, int nx, int ny, int nz,
+                              double tau, lbm_storage s, unsigned flags, void* dev_pop,
+                              size_t pop_bytes, void* dev_aux, size_t aux_bytes,
+                              void* hip_stream);
+
+/* Host-only geometry check (no GPU needed), the same rule lbm_set_geometry
+ * applies.  material: host array of N bytes, material numbers of the guide
+ * (0 = no dynamics, 1 = fluid, 2 = no-slip bounce-back wall, 3 = moving
+ * bounce-back wall with the lattice's wall velocity).  periodic_mask: bit 0 =
+ * x, bit 1 = y, bit 2 = z.  Returns LBM_ERR_UNSUPPORTED for a material > 3,
+ * LBM_ERR_GEOMETRY if a fluid cell has, along some lattice velocity, a
+ * material-0 neighbour or a neighbour outside the box on a non-periodic axis. */
+lbm_status lbm_validate_geometry(lbm_descriptor d, int nx, int ny, int nz,
+                                 const uint8_t* material, unsigned periodic_mask);
+
+/* Install the material layout (host array of N bytes, copied) and the
+ * periodic axes; validated as lbm_validate_geometry.  sync.  Invalidates the
+ * populations: call lbm_init_equilibrium or lbm_set_populations next. */
+lbm_status lbm_set_geometry(lbm_lattice* h, const uint8_t* material, unsigned periodic_mask);
+
+/* Wall velocity u_w (3 doubles, host) of every material-3 cell.  Bounce-back
+ * across a link (x, x+c_i) to a moving wall returns f*_i - 2 w_i rho(x) (c_i.u_w)/c_s^2. */
+lbm_status lbm_set_wall_velocity(lbm_lattice* h, const double u_w[3]);
+
+/* Uniform body acceleration g (3 doubles, host) for Guo forcing: the
+ * collision uses u = j/rho + g/2 and adds the Guo term with force density
+ * rho*g.  g = 0 gives plain BGK. */
+lbm_status lbm_set_body_force(lbm_lattice* h, const double g[3]);
+
+/* Change the relaxation time (same rule as at creation). */
+lbm_status lbm_set_tau(lbm_lattice* h, double tau);
+
+/* Set every fluid cell to the second-order equilibrium of (rho, u).
+ * rho_dev: device double[N] or NULL (rho = 1); u_dev: device double[3*N]
+ * (component a of cell idx at a*N + idx) or NULL (u = 0).  async.  Resets the
+ * step counter and the propagation phase. */
+lbm_status lbm_init_equilibrium(lbm_lattice* h, const double* rho_dev, const double* u_dev);
+
+/* Overwrite the populations from device double[q*N] (natural layout: value of
+ * f_i at cell idx at i*N + idx, not shifted), rounded to the storage type.
+ * async.  Resets the step counter and the propagation phase. */
+lbm_status lbm_set_populations(lbm_lattice* h, const double* f_dev);
+
+/* Decode the current populations into device double[q*N] in the natural
+ * layout of lbm_set_populations (unshifted; entries of non-fluid cells are 0).
+ * async. */
+lbm_status lbm_get_populations(lbm_lattice* h, double* f_dev);
+
+/* Advance n >= 0 full time steps (collide + stream), enqueued on the lattice's
+ * stream.  async.  After the call the stored state is the post-streaming,
+ * pre-collision population set at time t0 + n. */
+lbm_status lbm_step(lbm_lattice* h, int n);
+
+/* Macroscopic fields of the current state into device buffers: rho_dev
+ * double[N] and u_dev double[3*N] (either may be NULL).  u is the
+ * force-shifted velocity j/rho + g/2 of the guide's Guo velocity shift.
+ * Non-fluid cells report 0.  Sums are accumulated in double.  async. */
+lbm_status lbm_moments(lbm_lattice* h, double* rho_dev, double* u_dev);
+
+/* Totals over fluid cells, reduced on the device in double: mass = sum rho,
+ * momentum = sum_i c_i f_i (unshifted), stats = {average rho, average energy
+ * (half the mean of |u|^2), max |u|} with the shifted u (may be NULL).  Host
+ * outputs; sync.  LBM_ERR_NONFINITE if any result is NaN or Inf. */
+lbm_status lbm_totals(lbm_lattice* h, double* mass, double momentum[3], double stats[3]);
+
+/* Number of steps taken since the last initialisation, and fluid cell count. */
+lbm_status lbm_get_info(const lbm_lattice* h, long long* steps, long long* fluid_cells);
+
+/* Release the handle (not the caller's buffers).  Waits for its stream. */
+lbm_status lbm_lattice_destroy(lbm_lattice* h);
+
+const char* lbm_status_string(lbm_status st);
+/* Message of the last failed call on h ("" if none); h may be NULL for
+ * failures of lbm_lattice_create. */
+const char* lbm_last_error(const lbm_lattice* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

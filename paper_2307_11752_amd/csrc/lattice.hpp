@@ -1,0 +1,187 @@
+// lattice.hpp -- velocity sets, storage converters and the per-cell BGK + Guo
+// update used by the gfx950 kernels in lbm.hip.
+//
+// Method: OpenLB User Guide, release 1.6 (arXiv:2307.11752).  Velocity sets:
+// Core Concepts, "Descriptor" (the D2Q9 listing; D3Q19 is only drawn, so its
+// set is the standard one: rest, 6 face and 12 edge neighbours, weights 1/3,
+// 1/18, 1/36).  Collision: Introduction, "Lattice Boltzmann Methods" (BGK
+// operator) and the BGK listing of "Collision Operators".  Forcing: Simulation
+// Models, "Coupling Between Momentum and Energy Equations" (velocity shift
+// u + F/2 and the Guo forcing term).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Velocity sets.  Weights are stored as multiples of 1/36 so that both float
+// and double get the correctly rounded value of the exact fraction.
+// ---------------------------------------------------------------------------
+template <int Q>
+struct Vel;
+
+template <>
+struct Vel<9> {
+  static constexpr int D = 2;
+  static constexpr int cx[9] = {0, -1, -1, -1, 0, 1, 1, 1, 0};
+  static constexpr int cy[9] = {0, 1, 0, -1, -1, -1, 0, 1, 1};
+  static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  static constexpr int opp[9] = {0, 5, 6, 7, 8, 1, 2, 3, 4};
+  static constexpr int w36[9] = {16, 1, 4, 1, 4, 1, 4, 1, 4};
+};
+
+template <>
+struct Vel<19> {
+  static constexpr int D = 3;
+  static constexpr int cx[19] = {0, -1, 0, 0, -1, -1, -1, -1, 0, 0, 1, 0, 0, 1, 1, 1, 1, 0, 0};
+  static constexpr int cy[19] = {0, 0, -1, 0, -1, 1, 0, 0, -1, -1, 0, 1, 0, 1, -1, 0, 0, 1, 1};
+  static constexpr int cz[19] = {0, 0, 0, -1, 0, 0, -1, 1, -1, 1, 0, 0, 1, 0, 0, 1, -1, 1, -1};
+  static constexpr int opp[19] = {0, 10, 11, 12, 13, 14, 15, 16, 17, 18,
+                                  1, 2,  3,  4,  5,  6,  7,  8,  9};
+  static constexpr int w36[19] = {12, 2, 2, 2, 1, 1, 1, 1, 1, 1, 2, 2, 2, 1, 1, 1, 1, 1, 1};
+};
+
+template <int Q, typename T>
+__host__ __device__ constexpr T weight(int i) {
+  return T(Vel<Q>::w36[i]) / T(36);
+}
+
+// ---------------------------------------------------------------------------
+// Storage converters.  F64 storage computes in double, every other storage
+// type in float.
+// ---------------------------------------------------------------------------
+struct bf16s {
+  uint16_t bits;
+};
+
+template <typename S>
+struct Store;
+
+template <>
+struct Store<double> {
+  using T = double;
+  static __device__ __forceinline__ T load(const double* p) { return *p; }
+  static __device__ __forceinline__ void store(double* p, T v) { *p = v; }
+  static __device__ __forceinline__ double to_f64(double v) { return v; }
+  static __device__ __forceinline__ double from_f64(double v) { return v; }
+};
+
+template <>
+struct Store<float> {
+  using T = float;
+  static __device__ __forceinline__ T load(const float* p) { return *p; }
+  static __device__ __forceinline__ void store(float* p, T v) { *p = v; }
+  static __device__ __forceinline__ double to_f64(float v) { return (double)v; }
+  static __device__ __forceinline__ float from_f64(double v) { return (float)v; }
+};
+
+template <>
+struct Store<_Float16> {
+  using T = float;
+  static __device__ __forceinline__ T load(const _Float16* p) { return (float)*p; }
+  static __device__ __forceinline__ void store(_Float16* p, T v) { *p = (_Float16)v; }
+  static __device__ __forceinline__ double to_f64(_Float16 v) { return (double)(float)v; }
+  // double -> float -> half can round twice; only initialisation uses it.
+  static __device__ __forceinline__ _Float16 from_f64(double v) { return (_Float16)(float)v; }
+};
+
+// bfloat16: the upper half of an IEEE single; float -> bf16 rounds to nearest even.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float v) {
+  uint32_t u = __float_as_uint(v);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <>
+struct Store<bf16s> {
+  using T = float;
+  static __device__ __forceinline__ T load(const bf16s* p) {
+    return __uint_as_float((uint32_t)p->bits << 16);
+  }
+  static __device__ __forceinline__ void store(bf16s* p, T v) { p->bits = f32_to_bf16_rne(v); }
+  static __device__ __forceinline__ double to_f64(bf16s v) {
+    return (double)__uint_as_float((uint32_t)v.bits << 16);
+  }
+  static __device__ __forceinline__ bf16s from_f64(double v) {
+    bf16s r;
+    r.bits = f32_to_bf16_rne((float)v);
+    return r;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Link words.  One 32-bit word per cell: bit 31 marks a fluid cell, bit k-1
+// (k = 1..q-1) marks that the neighbour x + c_k is a bounce-back wall
+// (material 2 or 3), bit 30 that at least one of those walls moves; the
+// moving links themselves are in a second word per cell (same bit layout).
+// ---------------------------------------------------------------------------
+constexpr uint32_t LINK_FLUID = 1u << 31;
+constexpr uint32_t LINK_HAS_MOVING = 1u << 30;
+
+template <typename T>
+struct StepParams {
+  T omega;      // 1/tau
+  T kguo;       // 1 - omega/2
+  T g[3];       // body acceleration
+  T mw[19];     // 6 w_i (c_i . u_w): moving-wall momentum term per unit density
+  int has_force;
+  int has_moving;
+};
+
+// One BGK + Guo collision of a cell held in registers (in place).
+//   rho = base + sum f  (base = 1 when f stores f_i - w_i, else 0)
+//   u   = j/rho + g/2                                  (Guo velocity shift)
+//   feq_i - base*w_i = w_i (sum f + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u))
+//   f*_i = f_i + omega (feq_i - f_i) + (1 - omega/2) w_i (3 (c_i - u).F + 9 (c_i.u)(c_i.F))
+// with F = rho g.  Returns rho.
+template <int Q, bool SHIFT, typename T>
+__device__ __forceinline__ T collide(T (&f)[Q], const StepParams<T>& p) {
+  using V = Vel<Q>;
+  T sf = T(0), jx = T(0), jy = T(0), jz = T(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    sf += f[i];
+    if (V::cx[i] > 0) jx += f[i];
+    if (V::cx[i] < 0) jx -= f[i];
+    if (V::cy[i] > 0) jy += f[i];
+    if (V::cy[i] < 0) jy -= f[i];
+    if (V::cz[i] > 0) jz += f[i];
+    if (V::cz[i] < 0) jz -= f[i];
+  }
+  const T rho = SHIFT ? T(1) + sf : sf;
+  const T inv = T(1) / rho;
+  T ux = jx * inv, uy = jy * inv, uz = jz * inv;
+  if (p.has_force) {
+    ux += T(0.5) * p.g[0];
+    uy += T(0.5) * p.g[1];
+    uz += T(0.5) * p.g[2];
+  }
+  const T uu = ux * ux + uy * uy + uz * uz;
+  const T A = sf - T(1.5) * rho * uu;
+  const T om = p.omega;
+  T Fx = T(0), Fy = T(0), Fz = T(0), kuF = T(0);
+  if (p.has_force) {
+    Fx = rho * p.g[0];
+    Fy = rho * p.g[1];
+    Fz = rho * p.g[2];
+    kuF = ux * Fx + uy * Fy + uz * Fz;
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const T w = weight<Q, T>(i);
+    const T cu = T(V::cx[i]) * ux + T(V::cy[i]) * uy + T(V::cz[i]) * uz;
+    const T feq = w * (A + rho * cu * (T(3) + T(4.5) * cu));
+    T v = f[i] + om * (feq - f[i]);
+    if (p.has_force) {
+      const T cF = T(V::cx[i]) * Fx + T(V::cy[i]) * Fy + T(V::cz[i]) * Fz;
+      v += p.kguo * w * (T(3) * (cF - kuF) + T(9) * cu * cF);
+    }
+    f[i] = v;
+  }
+  return rho;
+}
+
+}  // namespace lbm

@@ -1,0 +1,888 @@
+// lbm.hip -- gfx950 kernels and the C ABI (include/lbm.h) of the fused BGK
+// collide-and-stream step with bounce-back walls, moving walls, periodic wrap
+// and Guo forcing.
+//
+// Propagation: in-place AA pattern on one structure-of-arrays population
+// buffer.  The stream equation of the guide (f_i(t+1, x+c_i) = f*_i(t, x),
+// Introduction, "Lattice Boltzmann Methods") is realised without a second
+// lattice by alternating two kernels:
+//
+//   phase 0 (natural layout, slot i of x holds f_i(x)):
+//     read  f_i = A[i][x];   collide;   write A[opp(i)][x] = f*_i
+//   phase 1 (swapped layout, slot opp(i) of x holds f*_i(x) of the last step):
+//     read  f_j = A[opp(j)][x - c_j]        (or A[j][x] if x - c_j is a wall)
+//     collide
+//     write A[i][x + c_i] = f*_i            (or A[opp(i)][x] if x + c_i is a wall)
+//
+// Each slot is read and written by exactly one cell per launch, so neither
+// kernel races and each population crosses HBM once per step in each
+// direction.  Halfway bounce-back (the wall lies half way along the link)
+// becomes a redirected slot inside the cell itself; a moving wall (material 3)
+// subtracts 2 w_i rho (c_i.u_w)/c_s^2 from the reflected population, applied
+// where the reflected value is written.  Periodic axes wrap the neighbour
+// index; fluid cells never touch a non-periodic edge (geometry check).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lattice.hpp"
+#include "lbm.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int RED_BLOCKS = 1024;
+constexpr int RED_THREADS = 256;
+constexpr int RED_FIELDS = 8;  // mass, jx, jy, jz, sum|u|^2, max|u|, fluid count, spare
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct AuxLayout {
+  size_t link, mov, partials, result, total;
+};
+
+inline AuxLayout aux_layout(size_t N) {
+  AuxLayout a;
+  a.link = 0;
+  a.mov = align256(a.link + 4 * N);
+  a.partials = align256(a.mov + 4 * N);
+  a.result = align256(a.partials + sizeof(double) * RED_BLOCKS * RED_FIELDS);
+  a.total = align256(a.result + sizeof(double) * RED_FIELDS);
+  return a;
+}
+
+inline int qof(int d) { return d == LBM_D2Q9 ? 9 : 19; }
+
+inline size_t storage_bytes(int s) {
+  switch (s) {
+    case LBM_STORE_F64: return 8;
+    case LBM_STORE_F32: return 4;
+    case LBM_STORE_F16: return 2;
+    case LBM_STORE_BF16: return 2;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour addressing.  Coordinates wrap on every axis; on non-periodic axes
+// fluid cells never sit on the edge, so the wrap is never taken there.
+// ---------------------------------------------------------------------------
+struct Nbr {
+  int X[3];
+  uint32_t R[3][3];  // R[dy+1][dz+1] = nx*(y' + ny*z')
+  __device__ __forceinline__ uint32_t at(int dx, int dy, int dz) const {
+    return (uint32_t)X[dx + 1] + R[dy + 1][dz + 1];
+  }
+};
+
+__device__ __forceinline__ Nbr make_nbr(int x, int y, int z, int nx, int ny, int nz) {
+  Nbr n;
+  n.X[0] = x == 0 ? nx - 1 : x - 1;
+  n.X[1] = x;
+  n.X[2] = x == nx - 1 ? 0 : x + 1;
+  const int Y[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
+  const int Z[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) n.R[a][b] = (uint32_t)nx * (uint32_t)(Y[a] + ny * Z[b]);
+  return n;
+}
+
+// ---------------------------------------------------------------------------
+// The fused step kernel.  One thread per cell; a block covers a run of up to
+// blockDim.x cells along x of one (y, z) row.
+//   MASKED = false: every cell is fluid (fully periodic box); no link words.
+// ---------------------------------------------------------------------------
+template <int Q, typename S, bool SHIFT, int PHASE, bool MASKED>
+__global__ void __launch_bounds__(256)
+    step_kernel(S* __restrict__ pop, const uint32_t* __restrict__ link,
+                const uint32_t* __restrict__ mov, int nx, int ny, int nz, uint32_t N, int nxb,
+                StepParams<typename Store<S>::T> p) {
+  using T = typename Store<S>::T;
+  using V = Vel<Q>;
+  const int row = (int)blockIdx.x / nxb;
+  const int xb = (int)blockIdx.x - row * nxb;
+  const int x = xb * (int)blockDim.x + (int)threadIdx.x;
+  if (x >= nx) return;
+  const int y = row % ny;
+  const int z = row / ny;
+  const uint32_t idx = (uint32_t)x + (uint32_t)nx * (uint32_t)(y + ny * z);
+
+  uint32_t lw = LINK_FLUID, mv = 0;
+  if (MASKED) {
+    lw = link[idx];
+    if (!(lw & LINK_FLUID)) return;
+    if (p.has_moving && (lw & LINK_HAS_MOVING)) mv = mov[idx];
+  }
+  const Nbr nb = make_nbr(x, y, z, nx, ny, nz);
+
+  T f[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    uint32_t off;
+    if (PHASE == 0) {
+      off = (uint32_t)i * N + idx;
+    } else {
+      const int o = V::opp[i];
+      off = (uint32_t)o * N + nb.at(-V::cx[i], -V::cy[i], -V::cz[i]);
+      if (MASKED && i > 0 && ((lw >> (o - 1)) & 1u)) off = (uint32_t)i * N + idx;
+    }
+    f[i] = Store<S>::load(pop + off);
+  }
+
+  const T rho = collide<Q, SHIFT, T>(f, p);
+
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    T v = f[i];
+    if (MASKED && i > 0 && ((mv >> (i - 1)) & 1u)) v -= rho * p.mw[i];
+    uint32_t off;
+    if (PHASE == 0) {
+      off = (uint32_t)V::opp[i] * N + idx;
+    } else {
+      off = (uint32_t)i * N + nb.at(V::cx[i], V::cy[i], V::cz[i]);
+      if (MASKED && i > 0 && ((lw >> (i - 1)) & 1u)) off = (uint32_t)V::opp[i] * N + idx;
+    }
+    Store<S>::store(pop + off, v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Decoding of the stored state (used off the per-step path).
+// ---------------------------------------------------------------------------
+template <int Q, typename S>
+__device__ __forceinline__ S load_phase(const S* pop, uint32_t lw, int i, uint32_t idx,
+                                        const Nbr& nb, int phase, uint32_t N) {
+  using V = Vel<Q>;
+  if (phase == 0 || i == 0) return pop[(uint32_t)i * N + idx];
+  const int o = V::opp[i];
+  if ((lw >> (o - 1)) & 1u) return pop[(uint32_t)i * N + idx];
+  return pop[(uint32_t)o * N + nb.at(-V::cx[i], -V::cy[i], -V::cz[i])];
+}
+
+__device__ __forceinline__ void cell_coords(uint32_t idx, int nx, int ny, int& x, int& y, int& z) {
+  x = (int)(idx % (uint32_t)nx);
+  const uint32_t r = idx / (uint32_t)nx;
+  y = (int)(r % (uint32_t)ny);
+  z = (int)(r / (uint32_t)ny);
+}
+
+// f (double, natural layout, unshifted) of every cell; zeros for non-fluid cells.
+template <int Q, typename S, bool SHIFT>
+__global__ void get_pop_kernel(const S* __restrict__ pop, const uint32_t* __restrict__ link,
+                               double* __restrict__ out, int nx, int ny, int nz, uint32_t N,
+                               int phase) {
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
+       idx += gridDim.x * blockDim.x) {
+    const uint32_t lw = link[idx];
+    int x, y, z;
+    cell_coords(idx, nx, ny, x, y, z);
+    const Nbr nb = make_nbr(x, y, z, nx, ny, nz);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      double v = 0.0;
+      if (lw & LINK_FLUID) {
+        v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, N));
+        if (SHIFT) v += weight<Q, double>(i);
+      }
+      out[(size_t)i * N + idx] = v;
+    }
+  }
+}
+
+// Populations from double natural layout; phase becomes 0.
+template <int Q, typename S, bool SHIFT>
+__global__ void set_pop_kernel(S* __restrict__ pop, const double* __restrict__ in, uint32_t N) {
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
+       idx += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      double v = in[(size_t)i * N + idx];
+      if (SHIFT) v -= weight<Q, double>(i);
+      pop[(size_t)i * N + idx] = Store<S>::from_f64(v);
+    }
+  }
+}
+
+// Second-order equilibrium of (rho, u), evaluated in double, on fluid cells.
+template <int Q, typename S, bool SHIFT>
+__global__ void init_eq_kernel(S* __restrict__ pop, const uint32_t* __restrict__ link,
+                               const double* __restrict__ rho_in, const double* __restrict__ u_in,
+                               uint32_t N) {
+  using V = Vel<Q>;
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
+       idx += gridDim.x * blockDim.x) {
+    const bool fluid = (link[idx] & LINK_FLUID) != 0;
+    const double rho = rho_in ? rho_in[idx] : 1.0;
+    double u[3] = {0.0, 0.0, 0.0};
+    if (u_in)
+      for (int a = 0; a < V::D; ++a) u[a] = u_in[(size_t)a * N + idx];
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double w = weight<Q, double>(i);
+      const double cu = V::cx[i] * u[0] + V::cy[i] * u[1] + V::cz[i] * u[2];
+      double feq = w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+      if (SHIFT) feq -= w;
+      pop[(size_t)i * N + idx] = Store<S>::from_f64(fluid ? feq : 0.0);
+    }
+  }
+}
+
+// rho and shifted u of every cell (double accumulation); zeros off the fluid.
+template <int Q, typename S, bool SHIFT>
+__global__ void moments_kernel(const S* __restrict__ pop, const uint32_t* __restrict__ link,
+                               double* __restrict__ rho_out, double* __restrict__ u_out, int nx,
+                               int ny, int nz, uint32_t N, int phase, double gx, double gy,
+                               double gz) {
+  using V = Vel<Q>;
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
+       idx += gridDim.x * blockDim.x) {
+    const uint32_t lw = link[idx];
+    double rho = 0.0, u[3] = {0.0, 0.0, 0.0};
+    if (lw & LINK_FLUID) {
+      int x, y, z;
+      cell_coords(idx, nx, ny, x, y, z);
+      const Nbr nb = make_nbr(x, y, z, nx, ny, nz);
+      double sf = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const double v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, N));
+        sf += v;
+        j[0] += V::cx[i] * v;
+        j[1] += V::cy[i] * v;
+        j[2] += V::cz[i] * v;
+      }
+      rho = SHIFT ? 1.0 + sf : sf;
+      u[0] = j[0] / rho + 0.5 * gx;
+      u[1] = j[1] / rho + 0.5 * gy;
+      u[2] = V::D == 3 ? j[2] / rho + 0.5 * gz : 0.0;
+    }
+    if (rho_out) rho_out[idx] = rho;
+    if (u_out) {
+      u_out[idx] = u[0];
+      u_out[(size_t)N + idx] = u[1];
+      u_out[2 * (size_t)N + idx] = u[2];
+    }
+  }
+}
+
+// Per-block partial totals in double: mass, momentum (unshifted sum c f),
+// sum |u|^2 and max |u| (shifted u), fluid count.
+template <int Q, typename S, bool SHIFT>
+__global__ void __launch_bounds__(RED_THREADS)
+    totals_partial_kernel(const S* __restrict__ pop, const uint32_t* __restrict__ link,
+                          double* __restrict__ partials, int nx, int ny, int nz, uint32_t N,
+                          int phase, double gx, double gy, double gz) {
+  using V = Vel<Q>;
+  double acc[RED_FIELDS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
+       idx += gridDim.x * blockDim.x) {
+    const uint32_t lw = link[idx];
+    if (!(lw & LINK_FLUID)) continue;
+    int x, y, z;
+    cell_coords(idx, nx, ny, x, y, z);
+    const Nbr nb = make_nbr(x, y, z, nx, ny, nz);
+    double sf = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, N));
+      sf += v;
+      j[0] += V::cx[i] * v;
+      j[1] += V::cy[i] * v;
+      j[2] += V::cz[i] * v;
+    }
+    const double rho = SHIFT ? 1.0 + sf : sf;
+    const double ux = j[0] / rho + 0.5 * gx, uy = j[1] / rho + 0.5 * gy;
+    const double uz = V::D == 3 ? j[2] / rho + 0.5 * gz : 0.0;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    acc[0] += rho;
+    acc[1] += j[0];
+    acc[2] += j[1];
+    acc[3] += j[2];
+    acc[4] += uu;
+    acc[5] = fmax(acc[5], sqrt(uu));
+    acc[6] += 1.0;
+  }
+  __shared__ double red[RED_FIELDS][RED_THREADS];
+#pragma unroll
+  for (int k = 0; k < RED_FIELDS; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < RED_FIELDS; ++k) {
+        if (k == 5)
+          red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + s]);
+        else
+          red[k][threadIdx.x] += red[k][threadIdx.x + s];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < RED_FIELDS) partials[blockIdx.x * RED_FIELDS + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Sum the per-block partials in a fixed order (deterministic).
+__global__ void __launch_bounds__(RED_THREADS)
+    totals_final_kernel(const double* __restrict__ partials, double* __restrict__ result,
+                        int nblocks) {
+  __shared__ double red[RED_FIELDS][RED_THREADS];
+  double acc[RED_FIELDS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) {
+#pragma unroll
+    for (int k = 0; k < RED_FIELDS; ++k) {
+      const double v = partials[b * RED_FIELDS + k];
+      acc[k] = (k == 5) ? fmax(acc[k], v) : acc[k] + v;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RED_FIELDS; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < RED_FIELDS; ++k) {
+        if (k == 5)
+          red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + s]);
+        else
+          red[k][threadIdx.x] += red[k][threadIdx.x + s];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < RED_FIELDS) result[threadIdx.x] = red[threadIdx.x][0];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Handle
+// ---------------------------------------------------------------------------
+struct lbm_lattice {
+  int desc = 0, q = 0, nx = 0, ny = 0, nz = 0;
+  size_t N = 0;
+  int storage = 0;
+  bool shifted = false;
+  double tau = 0.0, omega = 0.0;
+  double g[3] = {0, 0, 0}, uw[3] = {0, 0, 0};
+  void* pop = nullptr;
+  size_t pop_bytes = 0;
+  unsigned char* aux = nullptr;
+  size_t aux_bytes = 0;
+  AuxLayout lay{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool has_geometry = false, initialized = false, all_fluid = false, has_moving_cells = false;
+  unsigned periodic = 0;
+  int phase = 0;
+  long long steps = 0;
+  long long nfluid = 0;
+  int bx = 256, nxb = 1;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+lbm_status fail(lbm_lattice* h, lbm_status st, const std::string& msg) {
+  if (h)
+    h->err = msg;
+  else
+    g_create_error = msg;
+  return st;
+}
+
+#define HIP_TRY(h, call)                                                               \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail((h), LBM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool tau_ok(double tau) { return (std::isinf(tau) && tau > 0) || (std::isfinite(tau) && tau > 0.5); }
+
+template <int Q>
+lbm_status build_links(int nx, int ny, int nz, const uint8_t* mat, unsigned periodic,
+                       std::vector<uint32_t>* link, std::vector<uint32_t>* mov, long long* nfluid,
+                       bool* has_moving, std::string* why) {
+  using V = Vel<Q>;
+  const size_t N = (size_t)nx * ny * nz;
+  for (size_t i = 0; i < N; ++i)
+    if (mat[i] > 3) {
+      *why = "material " + std::to_string(mat[i]) + " at cell " + std::to_string(i) +
+             " is not supported (only 0..3)";
+      return LBM_ERR_UNSUPPORTED;
+    }
+  if (link) {
+    link->assign(N, 0u);
+    mov->assign(N, 0u);
+  }
+  long long nf = 0;
+  bool hm = false;
+  const int dims[3] = {nx, ny, nz};
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const size_t idx = (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z);
+        if (mat[idx] != 1) continue;
+        ++nf;
+        uint32_t w = LINK_FLUID, m = 0;
+        for (int i = 1; i < Q; ++i) {
+          int c[3] = {x + V::cx[i], y + V::cy[i], z + V::cz[i]};
+          for (int a = 0; a < 3; ++a) {
+            if (c[a] >= 0 && c[a] < dims[a]) continue;
+            if (!((periodic >> a) & 1u)) {
+              *why = "fluid cell (" + std::to_string(x) + "," + std::to_string(y) + "," +
+                     std::to_string(z) + ") streams out of the box along non-periodic axis " +
+                     std::to_string(a);
+              return LBM_ERR_GEOMETRY;
+            }
+            c[a] = (c[a] + dims[a]) % dims[a];
+          }
+          const uint8_t mn = mat[(size_t)c[0] + (size_t)nx * ((size_t)c[1] + (size_t)ny * c[2])];
+          if (mn == 0) {
+            *why = "fluid cell (" + std::to_string(x) + "," + std::to_string(y) + "," +
+                   std::to_string(z) + ") borders a material-0 cell";
+            return LBM_ERR_GEOMETRY;
+          }
+          if (mn == 2) w |= 1u << (i - 1);
+          if (mn == 3) {
+            w |= (1u << (i - 1)) | LINK_HAS_MOVING;
+            m |= 1u << (i - 1);
+            hm = true;
+          }
+        }
+        if (link) {
+          (*link)[idx] = w;
+          (*mov)[idx] = m;
+        }
+      }
+  *nfluid = nf;
+  *has_moving = hm;
+  return LBM_OK;
+}
+
+lbm_status check_dims(lbm_descriptor d, int nx, int ny, int nz, std::string* why) {
+  if (d != LBM_D2Q9 && d != LBM_D3Q19) {
+    *why = "unknown descriptor";
+    return LBM_ERR_ARG;
+  }
+  if (nx <= 0 || ny <= 0 || nz <= 0) {
+    *why = "lattice sizes must be positive";
+    return LBM_ERR_ARG;
+  }
+  if (d == LBM_D2Q9 && nz != 1) {
+    *why = "D2Q9 needs nz == 1";
+    return LBM_ERR_ARG;
+  }
+  const double cells = (double)nx * ny * nz;
+  if (cells * qof(d) >= 4294967296.0) {
+    *why = "q*N must stay below 2^32 (32-bit population offsets)";
+    return LBM_ERR_UNSUPPORTED;
+  }
+  return LBM_OK;
+}
+
+template <typename T>
+StepParams<T> make_params(const lbm_lattice* h) {
+  StepParams<T> p{};
+  p.omega = (T)h->omega;
+  p.kguo = (T)(1.0 - 0.5 * h->omega);
+  for (int a = 0; a < 3; ++a) p.g[a] = (T)h->g[a];
+  p.has_force = (h->g[0] != 0.0 || h->g[1] != 0.0 || h->g[2] != 0.0) ? 1 : 0;
+  const int q = h->q;
+  double uwdot = 0.0;
+  for (int i = 0; i < 19; ++i) p.mw[i] = T(0);
+  for (int i = 0; i < q; ++i) {
+    double w, cu;
+    if (q == 9) {
+      w = Vel<9>::w36[i] / 36.0;
+      cu = Vel<9>::cx[i] * h->uw[0] + Vel<9>::cy[i] * h->uw[1];
+    } else {
+      w = Vel<19>::w36[i] / 36.0;
+      cu = Vel<19>::cx[i] * h->uw[0] + Vel<19>::cy[i] * h->uw[1] + Vel<19>::cz[i] * h->uw[2];
+    }
+    p.mw[i] = (T)(6.0 * w * cu);  // 2 w_i (c_i.u_w) / c_s^2
+    uwdot += fabs(cu);
+  }
+  p.has_moving = (h->has_moving_cells && uwdot != 0.0) ? 1 : 0;
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// Typed dispatch
+// ---------------------------------------------------------------------------
+template <int Q, typename S, bool SHIFT>
+struct Ops {
+  using T = typename Store<S>::T;
+
+  static void step(lbm_lattice* h, int phase) {
+    const StepParams<T> p = make_params<T>(h);
+    S* pop = (S*)h->pop;
+    const uint32_t* link = (const uint32_t*)(h->aux + h->lay.link);
+    const uint32_t* mov = (const uint32_t*)(h->aux + h->lay.mov);
+    const dim3 grid((unsigned)(h->nxb * h->ny * h->nz)), block((unsigned)h->bx);
+    const uint32_t N = (uint32_t)h->N;
+    if (h->all_fluid) {
+      if (phase == 0)
+        hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 0, false>), grid, block, 0, h->stream, pop,
+                           link, mov, h->nx, h->ny, h->nz, N, h->nxb, p);
+      else
+        hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 1, false>), grid, block, 0, h->stream, pop,
+                           link, mov, h->nx, h->ny, h->nz, N, h->nxb, p);
+    } else {
+      if (phase == 0)
+        hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 0, true>), grid, block, 0, h->stream, pop,
+                           link, mov, h->nx, h->ny, h->nz, N, h->nxb, p);
+      else
+        hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 1, true>), grid, block, 0, h->stream, pop,
+                           link, mov, h->nx, h->ny, h->nz, N, h->nxb, p);
+    }
+  }
+
+  static unsigned blocks(size_t N) {
+    size_t b = (N + 255) / 256;
+    return (unsigned)(b > 65536 ? 65536 : (b == 0 ? 1 : b));
+  }
+
+  static void get_pop(lbm_lattice* h, double* out) {
+    hipLaunchKernelGGL((get_pop_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
+                       (const S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), out, h->nx,
+                       h->ny, h->nz, (uint32_t)h->N, h->phase);
+  }
+  static void set_pop(lbm_lattice* h, const double* in) {
+    hipLaunchKernelGGL((set_pop_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
+                       (S*)h->pop, in, (uint32_t)h->N);
+  }
+  static void init_eq(lbm_lattice* h, const double* rho, const double* u) {
+    hipLaunchKernelGGL((init_eq_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
+                       (S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), rho, u,
+                       (uint32_t)h->N);
+  }
+  static void moments(lbm_lattice* h, double* rho, double* u) {
+    hipLaunchKernelGGL((moments_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
+                       (const S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), rho, u, h->nx,
+                       h->ny, h->nz, (uint32_t)h->N, h->phase, h->g[0], h->g[1], h->g[2]);
+  }
+  static void totals(lbm_lattice* h) {
+    double* partials = (double*)(h->aux + h->lay.partials);
+    double* result = (double*)(h->aux + h->lay.result);
+    hipLaunchKernelGGL((totals_partial_kernel<Q, S, SHIFT>), dim3(RED_BLOCKS), dim3(RED_THREADS),
+                       0, h->stream, (const S*)h->pop, (const uint32_t*)(h->aux + h->lay.link),
+                       partials, h->nx, h->ny, h->nz, (uint32_t)h->N, h->phase, h->g[0],
+                       h->g[1], h->g[2]);
+    hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(RED_THREADS), 0, h->stream, partials,
+                       result, RED_BLOCKS);
+  }
+};
+
+struct OpTable {
+  void (*step)(lbm_lattice*, int);
+  void (*get_pop)(lbm_lattice*, double*);
+  void (*set_pop)(lbm_lattice*, const double*);
+  void (*init_eq)(lbm_lattice*, const double*, const double*);
+  void (*moments)(lbm_lattice*, double*, double*);
+  void (*totals)(lbm_lattice*);
+};
+
+template <int Q, typename S, bool SHIFT>
+OpTable table() {
+  using O = Ops<Q, S, SHIFT>;
+  return OpTable{O::step, O::get_pop, O::set_pop, O::init_eq, O::moments, O::totals};
+}
+
+template <int Q, bool SHIFT>
+OpTable table_for_storage(int s) {
+  switch (s) {
+    case LBM_STORE_F64: return table<Q, double, SHIFT>();
+    case LBM_STORE_F32: return table<Q, float, SHIFT>();
+    case LBM_STORE_F16: return table<Q, _Float16, SHIFT>();
+    default: return table<Q, bf16s, SHIFT>();
+  }
+}
+
+OpTable ops(const lbm_lattice* h) {
+  if (h->q == 9)
+    return h->shifted ? table_for_storage<9, true>(h->storage)
+                      : table_for_storage<9, false>(h->storage);
+  return h->shifted ? table_for_storage<19, true>(h->storage)
+                    : table_for_storage<19, false>(h->storage);
+}
+
+lbm_status launch_check(lbm_lattice* h) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(h, LBM_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+lbm_status enter(lbm_lattice* h) {
+  if (!h) return LBM_ERR_ARG;
+  h->err.clear();
+  HIP_TRY(h, hipSetDevice(h->device));
+  return LBM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+lbm_status lbm_required_bytes(lbm_descriptor d, int nx, int ny, int nz, lbm_storage s,
+                              size_t* pop_bytes, size_t* aux_bytes) {
+  std::string why;
+  lbm_status st = check_dims(d, nx, ny, nz, &why);
+  if (st) return fail(nullptr, st, why);
+  if (storage_bytes(s) == 0) return fail(nullptr, LBM_ERR_ARG, "unknown storage type");
+  const size_t N = (size_t)nx * ny * nz;
+  if (pop_bytes) *pop_bytes = align256((size_t)qof(d) * N * storage_bytes(s));
+  if (aux_bytes) *aux_bytes = aux_layout(N).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_validate_geometry(lbm_descriptor d, int nx, int ny, int nz,
+                                 const uint8_t* material, unsigned periodic_mask) {
+  std::string why;
+  lbm_status st = check_dims(d, nx, ny, nz, &why);
+  if (st) return fail(nullptr, st, why);
+  if (!material) return fail(nullptr, LBM_ERR_ARG, "material is NULL");
+  long long nf;
+  bool hm;
+  st = d == LBM_D2Q9
+           ? build_links<9>(nx, ny, nz, material, periodic_mask, nullptr, nullptr, &nf, &hm, &why)
+           : build_links<19>(nx, ny, nz, material, periodic_mask, nullptr, nullptr, &nf, &hm, &why);
+  if (st) return fail(nullptr, st, why);
+  return LBM_OK;
+}
+
+lbm_status lbm_lattice_create(lbm_lattice** out, lbm_descriptor d, int nx, int ny, int nz,
+                              double tau, lbm_storage s, unsigned flags, void* dev_pop,
+                              size_t pop_bytes, void* dev_aux, size_t aux_bytes,
+                              void* hip_stream) {
+  if (!out) return fail(nullptr, LBM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  size_t need_pop = 0, need_aux = 0;
+  lbm_status st = lbm_required_bytes(d, nx, ny, nz, s, &need_pop, &need_aux);
+  if (st) return st;
+  if (!tau_ok(tau)) return fail(nullptr, LBM_ERR_ARG, "tau must be > 0.5 (or +inf for pure streaming)");
+  if (flags & ~LBM_FLAG_SHIFTED) return fail(nullptr, LBM_ERR_ARG, "unknown flags");
+  if (!dev_pop || !dev_aux) return fail(nullptr, LBM_ERR_ARG, "device buffers must not be NULL");
+  if (pop_bytes < need_pop || aux_bytes < need_aux)
+    return fail(nullptr, LBM_ERR_ARG,
+                "buffers too small: need pop " + std::to_string(need_pop) + " aux " +
+                    std::to_string(need_aux));
+  if (((uintptr_t)dev_pop & 255u) || ((uintptr_t)dev_aux & 255u))
+    return fail(nullptr, LBM_ERR_ARG, "device buffers must be 256-byte aligned");
+  lbm_lattice* h = new (std::nothrow) lbm_lattice();
+  if (!h) return fail(nullptr, LBM_ERR_ARG, "out of host memory");
+  h->desc = d;
+  h->q = qof(d);
+  h->nx = nx;
+  h->ny = ny;
+  h->nz = nz;
+  h->N = (size_t)nx * ny * nz;
+  h->storage = s;
+  h->shifted = (flags & LBM_FLAG_SHIFTED) != 0;
+  h->tau = tau;
+  h->omega = std::isinf(tau) ? 0.0 : 1.0 / tau;
+  h->pop = dev_pop;
+  h->pop_bytes = pop_bytes;
+  h->aux = (unsigned char*)dev_aux;
+  h->aux_bytes = aux_bytes;
+  h->lay = aux_layout(h->N);
+  h->stream = (hipStream_t)hip_stream;
+  h->bx = nx >= 256 ? 256 : ((nx + 63) / 64) * 64;
+  h->nxb = (nx + h->bx - 1) / h->bx;
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(nullptr, LBM_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_geometry(lbm_lattice* h, const uint8_t* material, unsigned periodic_mask) {
+  lbm_status st = enter(h);
+  if (st) return st;
+  if (!material) return fail(h, LBM_ERR_ARG, "material is NULL");
+  if (periodic_mask > 7u) return fail(h, LBM_ERR_ARG, "periodic_mask uses bits 0..2 only");
+  std::vector<uint32_t> link, mov;
+  long long nf = 0;
+  bool hm = false;
+  std::string why;
+  st = h->q == 9 ? build_links<9>(h->nx, h->ny, h->nz, material, periodic_mask, &link, &mov, &nf,
+                                  &hm, &why)
+                 : build_links<19>(h->nx, h->ny, h->nz, material, periodic_mask, &link, &mov,
+                                   &nf, &hm, &why);
+  if (st) return fail(h, st, why);
+  HIP_TRY(h, hipMemcpyAsync(h->aux + h->lay.link, link.data(), 4 * h->N, hipMemcpyHostToDevice,
+                            h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->aux + h->lay.mov, mov.data(), 4 * h->N, hipMemcpyHostToDevice,
+                            h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  h->periodic = periodic_mask;
+  h->nfluid = nf;
+  h->has_moving_cells = hm;
+  h->all_fluid = (size_t)nf == h->N;
+  h->has_geometry = true;
+  h->initialized = false;
+  h->phase = 0;
+  h->steps = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_wall_velocity(lbm_lattice* h, const double u_w[3]) {
+  if (!h) return LBM_ERR_ARG;
+  if (!u_w) return fail(h, LBM_ERR_ARG, "u_w is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(u_w[a])) return fail(h, LBM_ERR_ARG, "u_w must be finite");
+  if (h->q == 9 && u_w[2] != 0.0) return fail(h, LBM_ERR_ARG, "D2Q9 wall velocity needs u_w[2] == 0");
+  for (int a = 0; a < 3; ++a) h->uw[a] = u_w[a];
+  return LBM_OK;
+}
+
+lbm_status lbm_set_body_force(lbm_lattice* h, const double g[3]) {
+  if (!h) return LBM_ERR_ARG;
+  if (!g) return fail(h, LBM_ERR_ARG, "g is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(g[a])) return fail(h, LBM_ERR_ARG, "g must be finite");
+  if (h->q == 9 && g[2] != 0.0) return fail(h, LBM_ERR_ARG, "D2Q9 body force needs g[2] == 0");
+  for (int a = 0; a < 3; ++a) h->g[a] = g[a];
+  return LBM_OK;
+}
+
+lbm_status lbm_set_tau(lbm_lattice* h, double tau) {
+  if (!h) return LBM_ERR_ARG;
+  if (!tau_ok(tau)) return fail(h, LBM_ERR_ARG, "tau must be > 0.5 (or +inf for pure streaming)");
+  h->tau = tau;
+  h->omega = std::isinf(tau) ? 0.0 : 1.0 / tau;
+  return LBM_OK;
+}
+
+lbm_status lbm_init_equilibrium(lbm_lattice* h, const double* rho_dev, const double* u_dev) {
+  lbm_status st = enter(h);
+  if (st) return st;
+  if (!h->has_geometry) return fail(h, LBM_ERR_STATE, "set the geometry first");
+  ops(h).init_eq(h, rho_dev, u_dev);
+  st = launch_check(h);
+  if (st) return st;
+  h->phase = 0;
+  h->steps = 0;
+  h->initialized = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_lattice* h, const double* f_dev) {
+  lbm_status st = enter(h);
+  if (st) return st;
+  if (!f_dev) return fail(h, LBM_ERR_ARG, "f_dev is NULL");
+  if (!h->has_geometry) return fail(h, LBM_ERR_STATE, "set the geometry first");
+  ops(h).set_pop(h, f_dev);
+  st = launch_check(h);
+  if (st) return st;
+  h->phase = 0;
+  h->steps = 0;
+  h->initialized = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_lattice* h, double* f_dev) {
+  lbm_status st = enter(h);
+  if (st) return st;
+  if (!f_dev) return fail(h, LBM_ERR_ARG, "f_dev is NULL");
+  if (!h->initialized) return fail(h, LBM_ERR_STATE, "lattice not initialised");
+  ops(h).get_pop(h, f_dev);
+  return launch_check(h);
+}
+
+lbm_status lbm_step(lbm_lattice* h, int n) {
+  lbm_status st = enter(h);
+  if (st) return st;
+  if (n < 0) return fail(h, LBM_ERR_ARG, "n must be >= 0");
+  if (!h->initialized) return fail(h, LBM_ERR_STATE, "initialise the populations first");
+  const OpTable t = ops(h);
+  for (int s = 0; s < n; ++s) {
+    t.step(h, h->phase);
+    h->phase ^= 1;
+  }
+  h->steps += n;
+  return launch_check(h);
+}
+
+lbm_status lbm_moments(lbm_lattice* h, double* rho_dev, double* u_dev) {
+  lbm_status st = enter(h);
+  if (st) return st;
+  if (!h->initialized) return fail(h, LBM_ERR_STATE, "lattice not initialised");
+  if (!rho_dev && !u_dev) return LBM_OK;
+  ops(h).moments(h, rho_dev, u_dev);
+  return launch_check(h);
+}
+
+lbm_status lbm_totals(lbm_lattice* h, double* mass, double momentum[3], double stats[3]) {
+  lbm_status st = enter(h);
+  if (st) return st;
+  if (!h->initialized) return fail(h, LBM_ERR_STATE, "lattice not initialised");
+  ops(h).totals(h);
+  st = launch_check(h);
+  if (st) return st;
+  double r[RED_FIELDS];
+  HIP_TRY(h, hipMemcpyAsync(r, h->aux + h->lay.result, sizeof(r), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  if (mass) *mass = r[0];
+  if (momentum)
+    for (int a = 0; a < 3; ++a) momentum[a] = r[1 + a];
+  const double nf = r[6];
+  if (stats) {
+    stats[0] = nf > 0 ? r[0] / nf : 0.0;
+    stats[1] = nf > 0 ? 0.5 * r[4] / nf : 0.0;
+    stats[2] = r[5];
+  }
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(r[k])) return fail(h, LBM_ERR_NONFINITE, "non-finite value in the totals");
+  return LBM_OK;
+}
+
+lbm_status lbm_get_info(const lbm_lattice* h, long long* steps, long long* fluid_cells) {
+  if (!h) return LBM_ERR_ARG;
+  if (steps) *steps = h->steps;
+  if (fluid_cells) *fluid_cells = h->nfluid;
+  return LBM_OK;
+}
+
+lbm_status lbm_lattice_destroy(lbm_lattice* h) {
+  if (!h) return LBM_ERR_ARG;
+  hipError_t e = hipSetDevice(h->device);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  delete h;
+  return e == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+const char* lbm_status_string(lbm_status st) {
+  switch (st) {
+    case LBM_OK: return "ok";
+    case LBM_ERR_ARG: return "invalid argument";
+    case LBM_ERR_GEOMETRY: return "geometry rejected";
+    case LBM_ERR_UNSUPPORTED: return "unsupported";
+    case LBM_ERR_HIP: return "HIP runtime error";
+    case LBM_ERR_STATE: return "invalid call order";
+    case LBM_ERR_NONFINITE: return "non-finite value";
+  }
+  return "unknown status";
+}
+
+const char* lbm_last_error(const lbm_lattice* h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

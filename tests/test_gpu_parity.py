@@ -1,0 +1,262 @@
+"""GPU parity: the gfx950 path (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Bars (derived in DESIGN.md, section "Parity bars"):
+* pure streaming (omega = 0, g = 0, u_w = 0), any storage, odd and even step
+  counts: bit-exact;
+* FP64 storage, full steps with forcing and moving walls: max |df| <= 1e-13;
+* one step from an exactly representable state, any storage: every population
+  within one storage ulp plus 64 compute-type eps of its weight;
+* FP32 storage, many steps: velocity rel-L2 <= 1e-5 (100 steps);
+* moments / totals of a state equal the oracle's of the same state to FP64
+  rounding.
+"""
+import numpy as np
+import pytest
+
+from _helpers import EPS_COMPUTE, encode_decode, rel_l2, representable, ulp_storage
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm GPU visible")
+    import paper_2307_11752_amd as P
+    from paper_2307_11752_amd import _lib
+
+    _lib.load()  # raises loudly if the HIP library was not built
+    return P
+
+
+from paper_2307_11752_amd import workloads as W  # noqa: E402
+
+CASES_3D = [
+    ((7, 5, 6), 0b000),
+    ((9, 6, 5), 0b001),
+    ((6, 7, 8), 0b101),
+    ((5, 4, 6), 0b111),
+    ((70, 9, 7), 0b011),   # more than one x-block of 64 threads, ragged tail
+    ((300, 4, 3), 0b111),  # two 256-wide x-blocks, ragged tail
+]
+CASES_2D = [
+    ((9, 7, 1), 0b00),
+    ((12, 10, 1), 0b01),
+    ((8, 9, 1), 0b11),
+    ((130, 5, 1), 0b01),
+]
+
+
+def _pair(orc, lbm, d, shape, periodic, tau, storage, shifted, seed, g=(0, 0, 0), uw=(0, 0, 0),
+          fill="random"):
+    """GPU lattice + oracle lattice with identical geometry and parameters."""
+    mat = W.random_geometry(d, shape, periodic, seed)
+    gpu = lbm.Lattice(d, shape, tau, storage=storage, shifted=shifted)
+    gpu.set_geometry(mat, periodic)
+    gpu.set_body_force(g)
+    gpu.set_wall_velocity(uw)
+    ref = orc.Lattice(d, mat, periodic, tau, g=g, u_wall=uw)
+    return gpu, ref, mat
+
+
+def _fluid(mat):
+    return mat == 1
+
+
+def _weights(orc, d):
+    return orc.descriptor(d)[1]
+
+
+# ---------------------------------------------------------------------------
+# Pure streaming: bit-exact for every storage, both propagation phases
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage,shifted", [("f64", False), ("f64", True), ("f32", False),
+                                             ("f32", True), ("f16", True), ("bf16", True),
+                                             ("f16", False)])
+@pytest.mark.parametrize("d,case", [(1, c) for c in CASES_3D] + [(0, c) for c in CASES_2D])
+def test_pure_streaming_bit_exact(orc, lbm, storage, shifted, d, case):
+    shape, periodic = case
+    print(f"[pure-streaming] d={d} shape={shape} periodic={periodic} {storage} shifted={shifted}",
+          flush=True)
+    gpu, ref, mat = _pair(orc, lbm, d, shape, periodic, float("inf"), storage, shifted, seed=17)
+    w = _weights(orc, d)
+    rng = np.random.default_rng(99)
+    q = len(w)
+    nx, ny, nz = shape
+    f0 = w[:, None, None, None] * (1 + rng.uniform(-0.3, 0.3, (q, nz, ny, nx)))
+    f0 = representable(f0, w, storage, shifted)
+    f0[:, ~_fluid(mat)] = 0.0
+    gpu.set_populations(f0)
+    back = gpu.get_populations().cpu().numpy()
+    assert np.array_equal(back, f0), "set/get round trip is not exact"
+    ref.set_populations(f0)
+    done = 0
+    for n in (1, 1, 2, 3):
+        gpu.step(n)
+        ref.step(n)
+        done += n
+        got = gpu.get_populations().cpu().numpy()
+        fl = _fluid(mat)
+        assert np.array_equal(got[:, fl], ref.f[:, fl]), f"mismatch after {done} steps"
+
+
+# ---------------------------------------------------------------------------
+# Initialisation
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage,shifted", [("f64", False), ("f64", True), ("f32", False),
+                                             ("f32", True), ("f16", True), ("bf16", True)])
+@pytest.mark.parametrize("d", [0, 1])
+def test_init_equilibrium(orc, lbm, storage, shifted, d):
+    shape, periodic = (CASES_3D[1] if d == 1 else CASES_2D[1])
+    gpu, ref, mat = _pair(orc, lbm, d, shape, periodic, 0.8, storage, shifted, seed=3)
+    rho = W.random_density(shape, 4)
+    u = W.random_velocity(shape, 5, dim=3 if d == 1 else 2)
+    gpu.init_equilibrium(rho, u)
+    ref.init_equilibrium(rho, u[: (3 if d == 1 else 2)])
+    got = gpu.get_populations().cpu().numpy()
+    w = _weights(orc, d)
+    expect = encode_decode(ref.f, w, storage, shifted)
+    fl = _fluid(mat)
+    tol = ulp_storage(np.abs(ref.f[:, fl]) + w[:, None], storage) + 4e-16
+    assert np.all(np.abs(got[:, fl] - expect[:, fl]) <= tol)
+
+
+# ---------------------------------------------------------------------------
+# FP64: full steps with forcing and moving walls
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shifted", [False, True])
+@pytest.mark.parametrize("d,case", [(1, c) for c in CASES_3D] + [(0, c) for c in CASES_2D])
+def test_fp64_full_steps(orc, lbm, shifted, d, case):
+    shape, periodic = case
+    print(f"[fp64] d={d} shape={shape} periodic={periodic} shifted={shifted}", flush=True)
+    g = (2e-4, -1e-4, 5e-5) if d == 1 else (2e-4, -1e-4, 0.0)
+    uw = (0.03, 0.0, -0.02) if d == 1 else (0.03, -0.01, 0.0)
+    gpu, ref, mat = _pair(orc, lbm, d, shape, periodic, 0.7, "f64", shifted, seed=21, g=g, uw=uw)
+    rho = W.random_density(shape, 8)
+    u = W.random_velocity(shape, 9, dim=3 if d == 1 else 2)
+    gpu.init_equilibrium(rho, u)
+    ref.init_equilibrium(rho, u[: (3 if d == 1 else 2)])
+    fl = _fluid(mat)
+    worst = 0.0
+    for n in (1, 1, 5, 13):
+        gpu.step(n)
+        ref.step(n)
+        got = gpu.get_populations().cpu().numpy()
+        err = float(np.max(np.abs(got[:, fl] - ref.f[:, fl])))
+        worst = max(worst, err)
+        assert err <= 1e-13, err
+    print(f"  max|df| = {worst:.3e}")
+    # moments and totals of the final state
+    rho_g, u_g = (t.cpu().numpy() for t in gpu.moments())
+    rho_o, u_o = ref.moments()
+    assert np.max(np.abs(rho_g - rho_o)) <= 1e-13
+    assert np.max(np.abs(u_g - u_o)) <= 1e-13
+    m_g, j_g, s_g = gpu.totals()
+    m_o, j_o, s_o = ref.totals()
+    assert abs(m_g - m_o) <= 1e-12 * m_o
+    np.testing.assert_allclose(j_g, j_o, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(s_g, s_o, rtol=1e-11, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# One step from an exactly representable state, every storage type
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage,shifted", [("f64", True), ("f32", False), ("f32", True),
+                                             ("f16", True), ("bf16", True)])
+@pytest.mark.parametrize("d,case", [(1, CASES_3D[0]), (1, CASES_3D[3]), (1, CASES_3D[4]),
+                                    (0, CASES_2D[0]), (0, CASES_2D[3])])
+@pytest.mark.parametrize("parity", [0, 1])
+def test_one_step_within_storage_ulp(orc, lbm, storage, shifted, d, case, parity):
+    shape, periodic = case
+    g = (3e-4, 1e-4, -2e-4) if d == 1 else (3e-4, 1e-4, 0.0)
+    uw = (0.04, 0.0, 0.01) if d == 1 else (0.04, 0.0, 0.0)
+    gpu, ref, mat = _pair(orc, lbm, d, shape, periodic, 0.6, storage, shifted, seed=33, g=g, uw=uw)
+    w = _weights(orc, d)
+    ref.init_equilibrium(W.random_density(shape, 1), W.random_velocity(shape, 2, dim=3 if d else 2)[: 3 if d else 2])
+    rng = np.random.default_rng(5)
+    f0 = ref.f * (1 + rng.uniform(-0.02, 0.02, ref.f.shape))  # off equilibrium
+    f0 = representable(f0, w, storage, shifted)
+    fl = _fluid(mat)
+    f0[:, ~fl] = 0.0
+    gpu.set_populations(f0)
+    if parity:  # move the GPU to the swapped layout with a pure-streaming step
+        gpu.set_tau(float("inf"))
+        ref_stream = orc.Lattice(d, mat, periodic, float("inf"))
+        ref_stream.set_populations(f0)
+        ref_stream.step(1)
+        gpu.set_body_force((0, 0, 0))
+        gpu.set_wall_velocity((0, 0, 0))
+        gpu.step(1)
+        gpu.set_tau(0.6)
+        gpu.set_body_force(g)
+        gpu.set_wall_velocity(uw)
+        f0 = ref_stream.f
+    ref.set_populations(f0)
+    gpu.step(1)
+    ref.step(1)
+    got = gpu.get_populations().cpu().numpy()[:, fl]
+    exp = ref.f[:, fl]
+    wq = np.broadcast_to(w[:, None], exp.shape)
+    stored = exp - wq if shifted else exp
+    tol = ulp_storage(stored, storage) + 64 * EPS_COMPUTE[storage] * wq
+    err = np.abs(got - exp)
+    print(f"[one-step] {storage} shifted={shifted} d={d} max err/tol = {np.max(err / tol):.3f}")
+    assert np.all(err <= tol)
+
+
+# ---------------------------------------------------------------------------
+# FP32: many steps
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shifted", [False, True])
+@pytest.mark.parametrize("d,case", [(1, CASES_3D[2]), (1, CASES_3D[4]), (0, CASES_2D[2])])
+def test_fp32_many_steps(orc, lbm, shifted, d, case):
+    shape, periodic = case
+    g = (1e-4, 0.0, 0.0)
+    uw = (0.05, 0.0, 0.0)
+    gpu, ref, mat = _pair(orc, lbm, d, shape, periodic, 0.8, "f32", shifted, seed=41, g=g, uw=uw)
+    u = W.random_velocity(shape, 6, amplitude=0.03, dim=3 if d else 2)
+    gpu.init_equilibrium(None, u)
+    ref.init_equilibrium(None, u[: 3 if d else 2])
+    gpu.step(100)
+    ref.step(100)
+    fl = _fluid(mat)
+    rho_g, u_g = (t.cpu().numpy() for t in gpu.moments())
+    rho_o, u_o = ref.moments()
+    e = rel_l2(u_g[:, fl], u_o[:, fl])
+    print(f"[fp32-100] d={d} shifted={shifted} u rel-L2 = {e:.3e}, "
+          f"rho max err = {np.max(np.abs(rho_g[fl] - rho_o[fl])):.3e}")
+    assert e <= 1e-5
+    assert np.max(np.abs(rho_g[fl] - rho_o[fl])) <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Call-order and argument errors through the ABI on the GPU
+# ---------------------------------------------------------------------------
+def test_state_errors(lbm):
+    from paper_2307_11752_amd import _lib
+
+    lat = lbm.Lattice(1, (4, 4, 4), 0.8)
+    with pytest.raises(_lib.LBMError) as e:
+        lat.step(1)
+    assert e.value.status == _lib.ERR_STATE
+    with pytest.raises(_lib.LBMError) as e:
+        lat.set_geometry(np.zeros((4, 4, 4), np.uint8) + 1, 0)
+    assert e.value.status == _lib.ERR_GEOMETRY
+    lat.set_geometry(np.ones((4, 4, 4), np.uint8), 7)
+    with pytest.raises(_lib.LBMError) as e:
+        lat.step(1)
+    assert e.value.status == _lib.ERR_STATE
+    lat.init_equilibrium()
+    lat.step(3)
+    assert lat.info() == (3, 64)
+    with pytest.raises(_lib.LBMError) as e:
+        lat.set_tau(0.5)
+    assert e.value.status == _lib.ERR_ARG
+    nan = np.full((19, 4, 4, 4), np.nan)
+    lat.set_populations(nan)
+    with pytest.raises(_lib.LBMError) as e:
+        lat.totals()
+    assert e.value.status == _lib.ERR_NONFINITE
