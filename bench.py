@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before timing, run one plain device-to-device copy of this many MiB "
+                         "(reference dispatch for scaling HBM counters)")
     return ap.parse_args()
 
 
@@ -135,6 +138,15 @@ def main():
                   "u_max_abs": float(np.max(np.abs(du))),
                   "rho_max_abs": float(np.max(np.abs(rho_g[fl] - rho_o[fl])))}
         del ref
+
+    if args.copy_calibration_mib > 0:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # --- GPU timing ---
     lat.init_equilibrium(None, wl.u0)
