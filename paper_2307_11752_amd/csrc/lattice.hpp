@@ -66,6 +66,8 @@ struct Store<double> {
   static __device__ __forceinline__ void store(double* p, T v) { *p = v; }
   static __device__ __forceinline__ double to_f64(double v) { return v; }
   static __device__ __forceinline__ double from_f64(double v) { return v; }
+  static __device__ __forceinline__ T cvt(double v) { return v; }
+  static __device__ __forceinline__ double pack(T v) { return v; }
 };
 
 template <>
@@ -75,6 +77,8 @@ struct Store<float> {
   static __device__ __forceinline__ void store(float* p, T v) { *p = v; }
   static __device__ __forceinline__ double to_f64(float v) { return (double)v; }
   static __device__ __forceinline__ float from_f64(double v) { return (float)v; }
+  static __device__ __forceinline__ T cvt(float v) { return v; }
+  static __device__ __forceinline__ float pack(T v) { return v; }
 };
 
 template <>
@@ -83,8 +87,9 @@ struct Store<_Float16> {
   static __device__ __forceinline__ T load(const _Float16* p) { return (float)*p; }
   static __device__ __forceinline__ void store(_Float16* p, T v) { *p = (_Float16)v; }
   static __device__ __forceinline__ double to_f64(_Float16 v) { return (double)(float)v; }
-  // double -> float -> half can round twice; only initialisation uses it.
-  static __device__ __forceinline__ _Float16 from_f64(double v) { return (_Float16)(float)v; }
+  static __device__ __forceinline__ _Float16 from_f64(double v) { return (_Float16)v; }
+  static __device__ __forceinline__ T cvt(_Float16 v) { return (float)v; }
+  static __device__ __forceinline__ _Float16 pack(T v) { return (_Float16)v; }
 };
 
 // bfloat16: the upper half of an IEEE single; float -> bf16 rounds to nearest even.
@@ -105,12 +110,38 @@ struct Store<bf16s> {
   static __device__ __forceinline__ double to_f64(bf16s v) {
     return (double)__uint_as_float((uint32_t)v.bits << 16);
   }
+  // double -> float -> bf16 (two roundings; only initialisation and
+  // set_populations use it).
   static __device__ __forceinline__ bf16s from_f64(double v) {
     bf16s r;
     r.bits = f32_to_bf16_rne((float)v);
     return r;
   }
+  static __device__ __forceinline__ T cvt(bf16s v) { return __uint_as_float((uint32_t)v.bits << 16); }
+  static __device__ __forceinline__ bf16s pack(T v) {
+    bf16s r;
+    r.bits = f32_to_bf16_rne(v);
+    return r;
+  }
 };
+
+// Non-temporal (cache-bypassing) single-value access in the compute type.
+template <typename S>
+__device__ __forceinline__ typename Store<S>::T load_nt(const S* p) {
+  return Store<S>::cvt(__builtin_nontemporal_load(p));
+}
+template <>
+__device__ __forceinline__ float load_nt<bf16s>(const bf16s* p) {
+  return __uint_as_float((uint32_t)__builtin_nontemporal_load((const uint16_t*)p) << 16);
+}
+template <typename S>
+__device__ __forceinline__ void store_nt(S* p, typename Store<S>::T v) {
+  __builtin_nontemporal_store(Store<S>::pack(v), p);
+}
+template <>
+__device__ __forceinline__ void store_nt<bf16s>(bf16s* p, float v) {
+  __builtin_nontemporal_store(f32_to_bf16_rne(v), (uint16_t*)p);
+}
 
 // ---------------------------------------------------------------------------
 // Link words.  One 32-bit word per cell: bit 31 marks a fluid cell, bit k-1

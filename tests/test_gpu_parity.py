@@ -48,12 +48,22 @@ CASES_2D = [
     ((8, 9, 1), 0b11),
     ((130, 5, 1), 0b01),
 ]
+# Fully fluid periodic boxes take the row/flat fast path when nx is a multiple
+# of the cells per lane (8 bytes / storage size) and a row fits 256 lanes;
+# the shapes cover one and many rows per block, 2..256 lanes per row, and
+# shapes that fall back to the per-cell kernel (nx not a multiple).
+FLUID_3D = [(8, 6, 5), (12, 5, 4), (64, 4, 3), (256, 3, 2), (512, 2, 3), (6, 5, 4), (20, 3, 7)]
+FLUID_2D = [(16, 10, 1), (128, 6, 1), (36, 7, 1), (10, 9, 1)]
 
 
 def _pair(orc, lbm, d, shape, periodic, tau, storage, shifted, seed, g=(0, 0, 0), uw=(0, 0, 0),
-          fill="random"):
+          fluid_only=False):
     """GPU lattice + oracle lattice with identical geometry and parameters."""
-    mat = W.random_geometry(d, shape, periodic, seed)
+    if fluid_only:
+        nx, ny, nz = shape
+        mat = np.ones((nz, ny, nx), np.uint8)
+    else:
+        mat = W.random_geometry(d, shape, periodic, seed)
     gpu = lbm.Lattice(d, shape, tau, storage=storage, shifted=shifted)
     gpu.set_geometry(mat, periodic)
     gpu.set_body_force(g)
@@ -101,6 +111,30 @@ def test_pure_streaming_bit_exact(orc, lbm, storage, shifted, d, case):
         got = gpu.get_populations().cpu().numpy()
         fl = _fluid(mat)
         assert np.array_equal(got[:, fl], ref.f[:, fl]), f"mismatch after {done} steps"
+
+
+@pytest.mark.parametrize("storage,shifted", [("f64", False), ("f32", False), ("f32", True),
+                                             ("f16", True), ("bf16", True)])
+@pytest.mark.parametrize("d,shape", [(1, s) for s in FLUID_3D] + [(0, s) for s in FLUID_2D])
+def test_pure_streaming_bit_exact_fluid_box(orc, lbm, storage, shifted, d, shape):
+    periodic = 0b111 if d == 1 else 0b011
+    print(f"[pure-streaming fluid] d={d} shape={shape} {storage} shifted={shifted}", flush=True)
+    gpu, ref, mat = _pair(orc, lbm, d, shape, periodic, float("inf"), storage, shifted, seed=1,
+                          fluid_only=True)
+    w = _weights(orc, d)
+    rng = np.random.default_rng(7)
+    nx, ny, nz = shape
+    f0 = w[:, None, None, None] * (1 + rng.uniform(-0.3, 0.3, (len(w), nz, ny, nx)))
+    f0 = representable(f0, w, storage, shifted)
+    gpu.set_populations(f0)
+    ref.set_populations(f0)
+    done = 0
+    for n in (1, 1, 2, 3):
+        gpu.step(n)
+        ref.step(n)
+        done += n
+        got = gpu.get_populations().cpu().numpy()
+        assert np.array_equal(got, ref.f), f"mismatch after {done} steps"
 
 
 # ---------------------------------------------------------------------------
@@ -161,19 +195,44 @@ def test_fp64_full_steps(orc, lbm, shifted, d, case):
     np.testing.assert_allclose(s_g, s_o, rtol=1e-11, atol=1e-15)
 
 
+@pytest.mark.parametrize("shifted", [False, True])
+@pytest.mark.parametrize("d,shape", [(1, s) for s in FLUID_3D] + [(0, s) for s in FLUID_2D])
+def test_fp64_full_steps_fluid_box(orc, lbm, shifted, d, shape):
+    periodic = 0b111 if d == 1 else 0b011
+    g = (2e-4, -1e-4, 5e-5) if d == 1 else (2e-4, -1e-4, 0.0)
+    gpu, ref, mat = _pair(orc, lbm, d, shape, periodic, 0.7, "f64", shifted, seed=2, g=g,
+                          fluid_only=True)
+    rho = W.random_density(shape, 8)
+    u = W.random_velocity(shape, 9, dim=3 if d == 1 else 2)
+    gpu.init_equilibrium(rho, u)
+    ref.init_equilibrium(rho, u[: (3 if d == 1 else 2)])
+    for n in (1, 1, 4, 9):
+        gpu.step(n)
+        ref.step(n)
+        got = gpu.get_populations().cpu().numpy()
+        err = float(np.max(np.abs(got - ref.f)))
+        assert err <= 1e-13, err
+
+
 # ---------------------------------------------------------------------------
 # One step from an exactly representable state, every storage type
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("storage,shifted", [("f64", True), ("f32", False), ("f32", True),
                                              ("f16", True), ("bf16", True)])
 @pytest.mark.parametrize("d,case", [(1, CASES_3D[0]), (1, CASES_3D[3]), (1, CASES_3D[4]),
-                                    (0, CASES_2D[0]), (0, CASES_2D[3])])
+                                    (0, CASES_2D[0]), (0, CASES_2D[3]),
+                                    (1, ((64, 4, 3), "fluid")), (1, ((12, 5, 4), "fluid")),
+                                    (0, ((128, 6, 1), "fluid"))])
 @pytest.mark.parametrize("parity", [0, 1])
 def test_one_step_within_storage_ulp(orc, lbm, storage, shifted, d, case, parity):
     shape, periodic = case
+    fluid_only = periodic == "fluid"
+    if fluid_only:
+        periodic = 0b111 if d == 1 else 0b011
     g = (3e-4, 1e-4, -2e-4) if d == 1 else (3e-4, 1e-4, 0.0)
     uw = (0.04, 0.0, 0.01) if d == 1 else (0.04, 0.0, 0.0)
-    gpu, ref, mat = _pair(orc, lbm, d, shape, periodic, 0.6, storage, shifted, seed=33, g=g, uw=uw)
+    gpu, ref, mat = _pair(orc, lbm, d, shape, periodic, 0.6, storage, shifted, seed=33, g=g, uw=uw,
+                          fluid_only=fluid_only)
     w = _weights(orc, d)
     ref.init_equilibrium(W.random_density(shape, 1), W.random_velocity(shape, 2, dim=3 if d else 2)[: 3 if d else 2])
     rng = np.random.default_rng(5)
@@ -211,12 +270,17 @@ def test_one_step_within_storage_ulp(orc, lbm, storage, shifted, d, case, parity
 # FP32: many steps
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("shifted", [False, True])
-@pytest.mark.parametrize("d,case", [(1, CASES_3D[2]), (1, CASES_3D[4]), (0, CASES_2D[2])])
+@pytest.mark.parametrize("d,case", [(1, CASES_3D[2]), (1, CASES_3D[4]), (0, CASES_2D[2]),
+                                    (1, ((64, 6, 5), "fluid")), (0, ((128, 16, 1), "fluid"))])
 def test_fp32_many_steps(orc, lbm, shifted, d, case):
     shape, periodic = case
+    fluid_only = periodic == "fluid"
+    if fluid_only:
+        periodic = 0b111 if d == 1 else 0b011
     g = (1e-4, 0.0, 0.0)
     uw = (0.05, 0.0, 0.0)
-    gpu, ref, mat = _pair(orc, lbm, d, shape, periodic, 0.8, "f32", shifted, seed=41, g=g, uw=uw)
+    gpu, ref, mat = _pair(orc, lbm, d, shape, periodic, 0.8, "f32", shifted, seed=41, g=g, uw=uw,
+                          fluid_only=fluid_only)
     u = W.random_velocity(shape, 6, amplitude=0.03, dim=3 if d else 2)
     gpu.init_equilibrium(None, u)
     ref.init_equilibrium(None, u[: 3 if d else 2])
