@@ -37,6 +37,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-steps", type=int, default=0,
+                    help="run exactly this many oracle steps (overrides --cpu-seconds)")
+    ap.add_argument("--variants", default="",
+                    help="comma list of storages compared with the oracle after the oracle's "
+                         "steps: f64, f32, f32s, f16s, bf16s (s = weight-shifted)")
+    ap.add_argument("--graph-steps", type=int, default=100,
+                    help="replay lbm_step in captured HIP graphs of this many steps (0 = off)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before timing, run one plain device-to-device copy of this many MiB "
                          "(reference dispatch for scaling HBM counters)")
@@ -67,7 +74,13 @@ def make_workload(args):
     return wl, storage, shifted, desc
 
 
-def cpu_baseline(wl, budget_s, u0):
+def parse_variant(v):
+    """'f16s' -> ('f16', True); 'f32' -> ('f32', False)."""
+    shifted = v.endswith("s") and v != "s"
+    return (v[:-1] if shifted else v), shifted
+
+
+def cpu_baseline(wl, budget_s, u0, fixed_steps=0):
     """Time the FP64 oracle on the same lattice for a bounded number of steps."""
     import numpy as np
 
@@ -84,7 +97,13 @@ def cpu_baseline(wl, budget_s, u0):
         ref.step(1)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 1000:
+        if fixed_steps > 0:
+            if steps >= fixed_steps:
+                break
+            if steps % 100 == 0:
+                print(f"[oracle] {steps}/{fixed_steps} steps, {el:.0f} s", file=sys.stderr,
+                      flush=True)
+        elif el >= budget_s or steps >= 1000:
             break
     cores = oracle.num_threads()
     return ref, steps, el, nfluid, cores
@@ -108,36 +127,58 @@ def main():
     N = nx * ny * nz
     q = 9 if wl.descriptor == 0 else 19
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()  # default priority; capturable for graph replay
 
-    lat = P.Lattice(wl.descriptor, wl.shape, wl.tau, storage=storage, shifted=shifted,
-                    stream=stream)
-    lat.set_geometry(wl.material, wl.periodic)
-    lat.set_body_force(wl.g)
-    lat.set_wall_velocity(wl.u_wall)
+    def make_lattice(st, sh):
+        lt = P.Lattice(wl.descriptor, wl.shape, wl.tau, storage=st, shifted=sh, stream=stream)
+        lt.set_geometry(wl.material, wl.periodic)
+        lt.set_body_force(wl.g)
+        lt.set_wall_velocity(wl.u_wall)
+        if args.graph_steps:
+            lt.set_graph_steps(args.graph_steps)
+        return lt
+
+    lat = make_lattice(storage, shifted)
     _, nfluid = lat.info()
     masked = nfluid != N
 
     # --- oracle CPU baseline (rank 0, N=1), and a full-size parity sample ---
     cpu = None
     parity = None
+    variants_err = None
     if not args.no_cpu_baseline:
-        ref, csteps, cel, cfluid, cores = cpu_baseline(wl, args.cpu_seconds, wl.u0)
+        ref, csteps, cel, cfluid, cores = cpu_baseline(wl, args.cpu_seconds, wl.u0,
+                                                       args.oracle_steps)
         cpu = {"value": round(N * csteps / cel / 1e6, 3), "unit": "MLUPS", "cores": cores,
                "kind": "oracle",
                "sample": f"{csteps} steps of the full {nx}x{ny}x{nz} lattice (FP64 oracle, "
                          f"{cel:.1f} s wall, OpenMP over z-planes)"}
-        lat.init_equilibrium(None, wl.u0)
-        lat.step(csteps)
-        rho_g, u_g = (t.cpu().numpy() for t in lat.moments())
         rho_o, u_o = ref.moments()
         fl = wl.material == 1
-        du = u_g[:, fl] - u_o[:, fl]
-        parity = {"steps": csteps,
-                  "u_rel_l2": float(np.linalg.norm(du) / max(np.linalg.norm(u_o[:, fl]), 1e-300)),
-                  "u_max_abs": float(np.max(np.abs(du))),
-                  "rho_max_abs": float(np.max(np.abs(rho_g[fl] - rho_o[fl])))}
-        del ref
+
+        def error_of(lt):
+            lt.init_equilibrium(None, wl.u0)
+            m0 = lt.totals()[0]
+            lt.step(csteps)
+            rho_g, u_g = (t.cpu().numpy() for t in lt.moments())
+            m1 = lt.totals()[0]
+            du = u_g[:, fl] - u_o[:, fl]
+            return {"steps": csteps,
+                    "u_rel_l2": float(np.linalg.norm(du) / max(np.linalg.norm(u_o[:, fl]), 1e-300)),
+                    "u_max_abs": float(np.max(np.abs(du))),
+                    "rho_max_abs": float(np.max(np.abs(rho_g[fl] - rho_o[fl]))),
+                    "mass_drift_rel": (m1 - m0) / m0}
+
+        parity = error_of(lat)
+        if args.variants:
+            variants_err = {}
+            for v in args.variants.split(","):
+                st, sh = parse_variant(v.strip())
+                lt = make_lattice(st, sh)
+                variants_err[v.strip()] = error_of(lt)
+                lt.close()
+                del lt
+        del ref, rho_o, u_o
 
     if args.copy_calibration_mib > 0:
         nb = args.copy_calibration_mib << 20
@@ -209,6 +250,7 @@ def main():
                      "kernel": f"step_kernel<Q={q},{storage}{',shifted' if shifted else ''}>"},
         "cpu_baseline": cpu,
         "oracle_parity": parity,
+        "storage_error_vs_oracle": variants_err,
         "checks": extra,
         "paper_context": {"value": 17.2699, "unit": "MLUPs",
                           "what": "guide console log, bstep2d D2Q9, unstated hardware/precision"},

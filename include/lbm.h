@@ -140,6 +140,14 @@ lbm_status lbm_get_populations(lbm_lattice* h, double* f_dev);
  * pre-collision population set at time t0 + n. */
 lbm_status lbm_step(lbm_lattice* h, int n);
 
+/* Replay lbm_step in captured HIP graphs of `steps` time steps (even, > 0;
+ * 0 = direct launches, the default).  lbm_step(n) then launches whole graphs
+ * for as many full runs of `steps` as n holds and the rest directly.  Needs a
+ * non-null stream (graph capture); the graph is rebuilt after any change of
+ * tau, force, wall velocity or geometry.  Results are identical to direct
+ * launches (same kernels, same arguments). */
+lbm_status lbm_set_graph_steps(lbm_lattice* h, int steps);
+
 /* Macroscopic fields of the current state into device buffers: rho_dev
  * double[N] and u_dev double[3*N] (either may be NULL).  u is the
  * force-shifted velocity j/rho + g/2 of the guide's Guo velocity shift.

@@ -51,6 +51,7 @@ SIGNATURES = {
     "lbm_set_populations": ([_P, _P], _I),
     "lbm_get_populations": ([_P, _P], _I),
     "lbm_step": ([_P, _I], _I),
+    "lbm_set_graph_steps": ([_P, _I], _I),
     "lbm_moments": ([_P, _P, _P], _I),
     "lbm_totals": ([_P, _P, _P, _P], _I),
     "lbm_get_info": ([_P, _PLL, _PLL], _I),

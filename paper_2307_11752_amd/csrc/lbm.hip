@@ -546,6 +546,10 @@ struct lbm_lattice {
   long long steps = 0;
   long long nfluid = 0;
   int bx = 256, nxb = 1;
+  // Replay of a captured run of graph_steps steps (0 = direct launches).  The
+  // graph bakes in the kernel arguments, so any parameter change drops it.
+  int graph_steps = 0;
+  hipGraphExec_t graph = nullptr;
   std::string err;
 };
 
@@ -800,6 +804,13 @@ lbm_status launch_check(lbm_lattice* h) {
   return LBM_OK;
 }
 
+void drop_graph(lbm_lattice* h) {
+  if (h->graph) {
+    (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+  }
+}
+
 lbm_status enter(lbm_lattice* h) {
   if (!h) return LBM_ERR_ARG;
   h->err.clear();
@@ -907,6 +918,7 @@ lbm_status lbm_set_geometry(lbm_lattice* h, const uint8_t* material, unsigned pe
   HIP_TRY(h, hipMemcpyAsync(h->aux + h->lay.mov, mov.data(), 4 * h->N, hipMemcpyHostToDevice,
                             h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
+  drop_graph(h);
   h->periodic = periodic_mask;
   h->nfluid = nf;
   h->has_moving_cells = hm;
@@ -925,6 +937,7 @@ lbm_status lbm_set_wall_velocity(lbm_lattice* h, const double u_w[3]) {
     if (!std::isfinite(u_w[a])) return fail(h, LBM_ERR_ARG, "u_w must be finite");
   if (h->q == 9 && u_w[2] != 0.0) return fail(h, LBM_ERR_ARG, "D2Q9 wall velocity needs u_w[2] == 0");
   for (int a = 0; a < 3; ++a) h->uw[a] = u_w[a];
+  drop_graph(h);
   return LBM_OK;
 }
 
@@ -935,6 +948,7 @@ lbm_status lbm_set_body_force(lbm_lattice* h, const double g[3]) {
     if (!std::isfinite(g[a])) return fail(h, LBM_ERR_ARG, "g must be finite");
   if (h->q == 9 && g[2] != 0.0) return fail(h, LBM_ERR_ARG, "D2Q9 body force needs g[2] == 0");
   for (int a = 0; a < 3; ++a) h->g[a] = g[a];
+  drop_graph(h);
   return LBM_OK;
 }
 
@@ -943,6 +957,7 @@ lbm_status lbm_set_tau(lbm_lattice* h, double tau) {
   if (!tau_ok(tau)) return fail(h, LBM_ERR_ARG, "tau must be > 0.5 (or +inf for pure streaming)");
   h->tau = tau;
   h->omega = std::isinf(tau) ? 0.0 : 1.0 / tau;
+  drop_graph(h);
   return LBM_OK;
 }
 
@@ -988,12 +1003,53 @@ lbm_status lbm_step(lbm_lattice* h, int n) {
   if (n < 0) return fail(h, LBM_ERR_ARG, "n must be >= 0");
   if (!h->initialized) return fail(h, LBM_ERR_STATE, "initialise the populations first");
   const OpTable t = ops(h);
-  for (int s = 0; s < n; ++s) {
+  int left = n;
+  if (h->graph_steps > 0 && n >= h->graph_steps) {
+    // The captured run starts in phase 0 and has an even length, so it can be
+    // replayed whenever the lattice is in phase 0.
+    if (h->phase != 0) {
+      t.step(h, 1);
+      h->phase = 0;
+      --left;
+    }
+    if (!h->graph && left >= h->graph_steps) {
+      hipGraph_t g = nullptr;
+      HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      for (int s = 0; s < h->graph_steps; ++s) t.step(h, s & 1);
+      hipError_t e = hipStreamEndCapture(h->stream, &g);
+      if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(h, LBM_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      }
+      e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        h->graph = nullptr;
+        return fail(h, LBM_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      }
+    }
+    while (h->graph && left >= h->graph_steps) {
+      HIP_TRY(h, hipGraphLaunch(h->graph, h->stream));
+      left -= h->graph_steps;
+    }
+  }
+  for (int s = 0; s < left; ++s) {
     t.step(h, h->phase);
     h->phase ^= 1;
   }
   h->steps += n;
   return launch_check(h);
+}
+
+lbm_status lbm_set_graph_steps(lbm_lattice* h, int steps) {
+  lbm_status st = enter(h);
+  if (st) return st;
+  if (steps < 0 || (steps & 1)) return fail(h, LBM_ERR_ARG, "graph length must be even and >= 0");
+  if (steps > 0 && h->stream == nullptr)
+    return fail(h, LBM_ERR_ARG, "graph replay needs a created (non-null) stream");
+  drop_graph(h);
+  h->graph_steps = steps;
+  return LBM_OK;
 }
 
 lbm_status lbm_moments(lbm_lattice* h, double* rho_dev, double* u_dev) {
@@ -1040,6 +1096,7 @@ lbm_status lbm_lattice_destroy(lbm_lattice* h) {
   if (!h) return LBM_ERR_ARG;
   hipError_t e = hipSetDevice(h->device);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  drop_graph(h);
   delete h;
   return e == hipSuccess ? LBM_OK : LBM_ERR_HIP;
 }

@@ -123,47 +123,57 @@ class Lattice:
             raise ValueError(f"expected {n} values, got {t.numel()}")
         return t
 
+    # All torch work of a call (staging copies, output allocation) is ordered on
+    # the lattice's stream, the stream the library launches on.
     def init_equilibrium(self, rho=None, u=None):
         """rho: N values or None (1); u: (dim or 3, N...) values or None (0)."""
-        r = self._dev64(rho, self.N)
-        uu = None
-        if u is not None:
-            ut = torch.as_tensor(u, dtype=torch.float64).reshape(-1, self.N)
-            full = torch.zeros((3, self.N), dtype=torch.float64)
-            full[: ut.shape[0]] = ut.cpu() if ut.device.type != "cpu" else ut
-            uu = full.to(self.device)
         with torch.cuda.stream(self.stream):
+            r = self._dev64(rho, self.N)
+            uu = None
+            if u is not None:
+                ut = torch.as_tensor(u, dtype=torch.float64).reshape(-1, self.N)
+                full = torch.zeros((3, self.N), dtype=torch.float64)
+                full[: ut.shape[0]] = ut.cpu() if ut.device.type != "cpu" else ut
+                uu = full.to(self.device)
             self._chk(self.lib.lbm_init_equilibrium(
                 self.h, None if r is None else ctypes.c_void_p(r.data_ptr()),
                 None if uu is None else ctypes.c_void_p(uu.data_ptr())))
-        self.stream.synchronize()
+            self.stream.synchronize()
 
     def set_populations(self, f):
-        t = self._dev64(f, self.q * self.N)
-        self._chk(self.lib.lbm_set_populations(self.h, ctypes.c_void_p(t.data_ptr())))
-        self.stream.synchronize()
+        with torch.cuda.stream(self.stream):
+            t = self._dev64(f, self.q * self.N)
+            self._chk(self.lib.lbm_set_populations(self.h, ctypes.c_void_p(t.data_ptr())))
+            self.stream.synchronize()
 
     # -- hot path -----------------------------------------------------------
     def step(self, n=1):
         self._chk(self.lib.lbm_step(self.h, int(n)))
 
+    def set_graph_steps(self, steps):
+        """Replay lbm_step in captured HIP graphs of `steps` steps (0 = off)."""
+        self._chk(self.lib.lbm_set_graph_steps(self.h, int(steps)))
+
     # -- read-back ----------------------------------------------------------
     def get_populations(self):
         """Populations in natural layout, float64 tensor (q, nz, ny, nx) on the GPU."""
-        out = torch.empty((self.q, self.nz, self.ny, self.nx), dtype=torch.float64,
-                          device=self.device)
-        self.stream.synchronize()
-        self._chk(self.lib.lbm_get_populations(self.h, ctypes.c_void_p(out.data_ptr())))
-        self.stream.synchronize()
+        with torch.cuda.stream(self.stream):
+            out = torch.empty((self.q, self.nz, self.ny, self.nx), dtype=torch.float64,
+                              device=self.device)
+            self._chk(self.lib.lbm_get_populations(self.h, ctypes.c_void_p(out.data_ptr())))
+            self.stream.synchronize()
         return out
 
     def moments(self):
         """(rho (nz,ny,nx), u (3,nz,ny,nx)) float64 tensors on the GPU."""
-        rho = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
-        u = torch.empty((3, self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
-        self._chk(self.lib.lbm_moments(self.h, ctypes.c_void_p(rho.data_ptr()),
-                                       ctypes.c_void_p(u.data_ptr())))
-        self.stream.synchronize()
+        with torch.cuda.stream(self.stream):
+            rho = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64,
+                              device=self.device)
+            u = torch.empty((3, self.nz, self.ny, self.nx), dtype=torch.float64,
+                            device=self.device)
+            self._chk(self.lib.lbm_moments(self.h, ctypes.c_void_p(rho.data_ptr()),
+                                           ctypes.c_void_p(u.data_ptr())))
+            self.stream.synchronize()
         return rho, u
 
     def totals(self):

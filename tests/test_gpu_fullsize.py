@@ -1,0 +1,128 @@
+"""Parity at the benchmark's full sizes and launch configuration.
+
+The oracle runs the same full lattices for a few steps (odd and even counts,
+so both propagation phases and both stored layouts are compared) from the same
+seeded initial fields; every population of every fluid cell is compared.  The
+lid-driven cavity runs its full 2000 steps.
+
+Bar after n steps from an equilibrium initialisation, storage type S:
+|df| <= (n + 1) * (G ulp_S(max |stored value|) + 64 eps_compute w_i), G = 4.
+Each rounding to storage (the initial state and every step) costs at most half
+an ulp at the scale of the data; the collision then mixes the independent
+rounding errors of all q inputs of a cell into every output, the largest term
+being omega w_0 sum_j df_j of the rest population: at omega = 1/0.7,
+w_0 = 1/3, q = 19 and errors of standard deviation ulp/sqrt(12), a 6-sigma
+excursion (1e8 samples) is 1.43 * (1/3) * sqrt(19) * 0.29 * 6 = 3.6 ulp, plus
+the fresh half ulp: G = 4.  FP64 storage: |df| <= 1e-12 after 2000 steps.
+"""
+import numpy as np
+import pytest
+
+from _helpers import EPS_COMPUTE, ulp_storage
+
+GAIN = 4.0
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm GPU visible")
+    import paper_2307_11752_amd as P
+    from paper_2307_11752_amd import _lib
+
+    _lib.load()
+    return P
+
+
+from paper_2307_11752_amd import workloads as W  # noqa: E402
+
+
+def _compare(gpu, ref, wl, storage, shifted, nsteps, w):
+    got = gpu.get_populations()
+    fl_np = wl.material == 1
+    fl = torch.as_tensor(fl_np, device=got.device)
+    g = got[:, fl].cpu().numpy()
+    del got
+    e = ref.f[:, fl_np]
+    wq = np.broadcast_to(w[:, None], e.shape)
+    stored = e - wq if shifted else e
+    scale = ulp_storage(np.max(np.abs(stored)), storage)
+    tol = (nsteps + 1) * (GAIN * scale + 64 * EPS_COMPUTE[storage] * wq)
+    err = np.abs(g - e)
+    worst = float(np.max(err / tol))
+    print(f"  {wl.name} {storage}{'-shifted' if shifted else ''} after {nsteps} steps: "
+          f"max|df| = {float(np.max(err)):.3e}, max err/tol = {worst:.3f}", flush=True)
+    assert worst <= 1.0
+
+
+@pytest.mark.parametrize("storage,shifted", [("f32", False), ("f16", True)])
+def test_tgv256_fullsize(orc, lbm, storage, shifted):
+    print(f"[fullsize] tgv3d 256^3 {storage} shifted={shifted}", flush=True)
+    wl = W.tgv3d(256, u0=0.05, tau=0.8)
+    w = orc.descriptor(1)[1]
+    gpu = lbm.Lattice(1, wl.shape, wl.tau, storage=storage, shifted=shifted)
+    gpu.set_geometry(wl.material, wl.periodic)
+    gpu.init_equilibrium(None, wl.u0)
+    ref = orc.Lattice(1, wl.material, wl.periodic, wl.tau)
+    ref.init_equilibrium(None, wl.u0)
+    done = 0
+    for n in (1, 2):
+        gpu.step(n)
+        ref.step(n)
+        done += n
+        _compare(gpu, ref, wl, storage, shifted, done, w)
+    gpu.close()
+
+
+@pytest.mark.parametrize("storage,shifted", [("f32", True), ("f16", True), ("bf16", True),
+                                             ("f32", False)])
+def test_channel_fullsize(orc, lbm, storage, shifted):
+    print(f"[fullsize] channel 512x128x128 {storage} shifted={shifted}", flush=True)
+    wl = W.channel_spheres()
+    w = orc.descriptor(1)[1]
+    # a developed-looking start: the equilibrium of a seeded random flow
+    u0 = W.random_velocity(wl.shape, 11, amplitude=0.02)
+    gpu = lbm.Lattice(1, wl.shape, wl.tau, storage=storage, shifted=shifted)
+    gpu.set_geometry(wl.material, wl.periodic)
+    gpu.set_body_force(wl.g)
+    gpu.init_equilibrium(None, u0)
+    ref = orc.Lattice(1, wl.material, wl.periodic, wl.tau, g=wl.g)
+    ref.init_equilibrium(None, u0)
+    done = 0
+    for n in (1, 2):
+        gpu.step(n)
+        ref.step(n)
+        done += n
+        _compare(gpu, ref, wl, storage, shifted, done, w)
+    gpu.close()
+
+
+def test_cavity_full_config(orc, lbm):
+    """Lid-driven cavity 64x64, FP64, tau = 0.6, lid 0.05, 2000 steps."""
+    print("[fullsize] cavity2d 64x64 FP64 2000 steps", flush=True)
+    wl = W.cavity2d(64)
+    gpu = lbm.Lattice(0, wl.shape, wl.tau, storage="f64")
+    gpu.set_geometry(wl.material, wl.periodic)
+    gpu.set_wall_velocity(wl.u_wall)
+    gpu.init_equilibrium()
+    ref = orc.Lattice(0, wl.material, wl.periodic, wl.tau, u_wall=wl.u_wall)
+    ref.init_equilibrium()
+    m0 = ref.totals()[0]
+    gpu.step(wl.steps)
+    ref.step(wl.steps)
+    fl = wl.material == 1
+    got = gpu.get_populations().cpu().numpy()
+    err = float(np.max(np.abs(got[:, fl] - ref.f[:, fl])))
+    rho_g, u_g = (t.cpu().numpy() for t in gpu.moments())
+    rho_o, u_o = ref.moments()
+    uerr = float(np.max(np.abs(u_g - u_o)))
+    m_g = gpu.totals()[0]
+    print(f"  max|df| = {err:.3e}, max|du| = {uerr:.3e}, mass drift GPU = {(m_g - m0) / m0:.2e}",
+          flush=True)
+    assert err <= 1e-12
+    assert uerr <= 1e-12
+    assert abs(m_g - m0) <= 1e-12 * m0
+    assert np.max(np.abs(u_o[0])) > 0.01  # the lid drives a vortex
