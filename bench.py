@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--variants", default="",
                     help="comma list of storages compared with the oracle after the oracle's "
                          "steps: f64, f32, f32s, f16s, bf16s (s = weight-shifted)")
+    ap.add_argument("--ref-steps", type=int, default=0,
+                    help="also run the FP64-storage GPU path (parity-tested against the oracle) "
+                         "for this many steps and state every --variants storage's error "
+                         "against it at that horizon")
     ap.add_argument("--graph-steps", type=int, default=100,
                     help="replay lbm_step in captured HIP graphs of this many steps (0 = off)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -180,6 +184,34 @@ def main():
                 del lt
         del ref, rho_o, u_o
 
+    ref_err = None
+    if args.ref_steps > 0 and args.variants:
+        fl = wl.material == 1
+        rl = make_lattice("f64", True)
+        rl.init_equilibrium(None, wl.u0)
+        rl.step(args.ref_steps)
+        rho_r, u_r = (t.cpu().numpy() for t in rl.moments())
+        rl.close()
+        del rl
+        ref_err = {"reference": f"FP64-storage GPU path, {args.ref_steps} steps", "variants": {}}
+        for v in args.variants.split(","):
+            st, sh = parse_variant(v.strip())
+            lt = make_lattice(st, sh)
+            lt.init_equilibrium(None, wl.u0)
+            m0 = lt.totals()[0]
+            lt.step(args.ref_steps)
+            rho_g, u_g = (t.cpu().numpy() for t in lt.moments())
+            m1 = lt.totals()[0]
+            lt.close()
+            du = u_g[:, fl] - u_r[:, fl]
+            ref_err["variants"][v.strip()] = {
+                "u_rel_l2": float(np.linalg.norm(du) / max(np.linalg.norm(u_r[:, fl]), 1e-300)),
+                "u_max_abs": float(np.max(np.abs(du))),
+                "rho_max_abs": float(np.max(np.abs(rho_g[fl] - rho_r[fl]))),
+                "mass_drift_rel": (m1 - m0) / m0}
+            del lt
+        del rho_r, u_r
+
     if args.copy_calibration_mib > 0:
         nb = args.copy_calibration_mib << 20
         src = torch.ones(nb, dtype=torch.uint8, device="cuda")
@@ -251,6 +283,7 @@ def main():
         "cpu_baseline": cpu,
         "oracle_parity": parity,
         "storage_error_vs_oracle": variants_err,
+        "storage_error_vs_f64_gpu": ref_err,
         "checks": extra,
         "paper_context": {"value": 17.2699, "unit": "MLUPs",
                           "what": "guide console log, bstep2d D2Q9, unstated hardware/precision"},

@@ -115,32 +115,46 @@ __global__ void __launch_bounds__(256)
   const int z = row / ny;
   const uint32_t idx = (uint32_t)x + (uint32_t)nx * (uint32_t)(y + ny * z);
 
+  const Nbr nb = make_nbr(x, y, z, nx, ny, nz);
   uint32_t lw = LINK_FLUID, mv = 0;
-  if (MASKED) {
+  T f[Q];
+  if (MASKED && PHASE == 1) {
+    // The neighbour loads do not wait for the link word (waiting would expose
+    // one memory latency per wave); a wall cell's lanes read values nobody
+    // uses, and the populations reflected by a wall are then re-read from the
+    // cell's own slots.
     lw = link[idx];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const uint32_t off = (uint32_t)V::opp[i] * N + nb.at(-V::cx[i], -V::cy[i], -V::cz[i]);
+      f[i] = V::cx[i] == 0 ? load_nt<S>(pop + off) : Store<S>::load(pop + off);
+    }
     if (!(lw & LINK_FLUID)) return;
     if (p.has_moving && (lw & LINK_HAS_MOVING)) mv = mov[idx];
-  }
-  const Nbr nb = make_nbr(x, y, z, nx, ny, nz);
-
-  T f[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    uint32_t off;
-    if (PHASE == 0) {
-      off = (uint32_t)i * N + idx;
-    } else {
-      const int o = V::opp[i];
-      off = (uint32_t)o * N + nb.at(-V::cx[i], -V::cy[i], -V::cz[i]);
-      if (MASKED && i > 0 && ((lw >> (o - 1)) & 1u)) off = (uint32_t)i * N + idx;
+    for (int i = 1; i < Q; ++i)
+      if ((lw >> (V::opp[i] - 1)) & 1u) f[i] = Store<S>::load(pop + (uint32_t)i * N + idx);
+  } else {
+    if (MASKED) {
+      lw = link[idx];
+      if (!(lw & LINK_FLUID)) return;
+      if (p.has_moving && (lw & LINK_HAS_MOVING)) mv = mov[idx];
     }
-    // Streaming data is touched once per launch: x-aligned accesses bypass the
-    // caches; x-shifted ones (phase 1, c_x != 0) share lines with the
-    // neighbouring wave and stay cached.
-    if (PHASE == 0 || V::cx[i] == 0)
-      f[i] = load_nt<S>(pop + off);
-    else
-      f[i] = Store<S>::load(pop + off);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      uint32_t off;
+      if (PHASE == 0)
+        off = (uint32_t)i * N + idx;
+      else
+        off = (uint32_t)V::opp[i] * N + nb.at(-V::cx[i], -V::cy[i], -V::cz[i]);
+      // Streaming data is touched once per launch: x-aligned accesses bypass
+      // the caches; x-shifted ones (phase 1, c_x != 0) share lines with the
+      // neighbouring wave and stay cached.
+      if (PHASE == 0 || V::cx[i] == 0)
+        f[i] = load_nt<S>(pop + off);
+      else
+        f[i] = Store<S>::load(pop + off);
+    }
   }
 
   const T rho = collide<Q, SHIFT, T>(f, p);
@@ -312,6 +326,73 @@ __global__ void __launch_bounds__(256)
                                   (raw8*)(pop + base + x0));
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Masked phase 0 (lattices with walls), same lane shape as the fluid path.
+// Every lane loads its C cells' slots aligned and non-temporal together with
+// their link words (waiting for the links first would expose one memory
+// latency per wave), collides the fluid cells and writes every slot back:
+// non-fluid cells keep their values, so each line is written whole and each
+// slot still has a single writer.
+// ---------------------------------------------------------------------------
+template <int C>
+struct LinkVec {
+  static __device__ __forceinline__ void load(const uint32_t* p, uint32_t (&lw)[C]) {
+    if constexpr (C == 1) {
+      lw[0] = __builtin_nontemporal_load(p);
+    } else if constexpr (C == 2) {
+      typedef uint32_t v2 __attribute__((ext_vector_type(2)));
+      const v2 v = __builtin_nontemporal_load((const v2*)p);
+      lw[0] = v.x;
+      lw[1] = v.y;
+    } else {
+      typedef uint32_t v4 __attribute__((ext_vector_type(4)));
+      const v4 v = __builtin_nontemporal_load((const v4*)p);
+      lw[0] = v.x;
+      lw[1] = v.y;
+      lw[2] = v.z;
+      lw[3] = v.w;
+    }
+  }
+};
+
+template <int Q, typename S, bool SHIFT>
+__global__ void __launch_bounds__(256)
+    step_p0_masked_kernel(S* __restrict__ pop, const uint32_t* __restrict__ link,
+                          const uint32_t* __restrict__ mov, uint32_t N,
+                          StepParams<typename Store<S>::T> p) {
+  using T = typename Store<S>::T;
+  using V = Vel<Q>;
+  constexpr int C = Pack8<S>::C;
+  const uint32_t c0 = (uint32_t)C * (blockIdx.x * blockDim.x + threadIdx.x);
+  if (c0 >= N) return;
+  // link words and populations are requested together: waiting for the links
+  // before issuing the population loads would expose one memory latency per wave
+  uint32_t lw[C];
+  LinkVec<C>::load(link + c0, lw);
+  S sv[Q][C];
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    Pack8<S>::unpack(__builtin_nontemporal_load((const raw8*)(pop + (uint32_t)i * N + c0)), sv[i]);
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    if (!(lw[k] & LINK_FLUID)) continue;
+    const uint32_t mv = (p.has_moving && (lw[k] & LINK_HAS_MOVING)) ? mov[c0 + k] : 0u;
+    T f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = Store<S>::cvt(sv[i][k]);
+    const T rho = collide<Q, SHIFT, T>(f, p);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      T v = f[i];
+      if (i > 0 && ((mv >> (i - 1)) & 1u)) v -= rho * p.mw[i];
+      sv[V::opp[i]][k] = Store<S>::pack(v);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    __builtin_nontemporal_store(Pack8<S>::pack(sv[i]), (raw8*)(pop + (uint32_t)i * N + c0));
 }
 
 // ---------------------------------------------------------------------------
@@ -712,6 +793,13 @@ struct Ops {
         hipLaunchKernelGGL((step_p1_rows_kernel<Q, S, SHIFT>), dim3(nb), dim3(rpb * tpr), lds,
                            h->stream, pop, h->nx, h->ny, h->nz, N, tpr, rpb, p);
       }
+    } else if (!h->all_fluid && h->N % C == 0 && h->N >= 65536 && phase == 0) {
+      // (small lattices are latency-bound: the per-cell kernel below, with
+      // more and smaller blocks, is faster there)
+      const unsigned threads = 128;
+      const unsigned nb = (unsigned)((h->N / C + threads - 1) / threads);
+      hipLaunchKernelGGL((step_p0_masked_kernel<Q, S, SHIFT>), dim3(nb), dim3(threads), 0,
+                         h->stream, pop, link, mov, N, p);
     } else if (h->all_fluid) {
       if (phase == 0)
         hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 0, false>), grid, block, 0, h->stream, pop,
