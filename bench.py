@@ -30,7 +30,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="tgv3d", choices=["tgv3d", "channel", "cavity"])
+    ap.add_argument("--workload", default="tgv3d",
+                    choices=["tgv3d", "channel", "cavity", "ensemble"])
     ap.add_argument("--storage", default=None, choices=[None, "f64", "f32", "f16", "bf16"])
     ap.add_argument("--shifted", type=int, default=None)
     ap.add_argument("--n", type=int, default=256, help="tgv3d edge length")
@@ -113,6 +114,114 @@ def cpu_baseline(wl, budget_s, u0, fixed_steps=0):
     return ref, steps, el, nfluid, cores
 
 
+def bench_ensemble(args):
+    """Batched ensemble: 256 periodic D3Q19 Taylor-Green lattices, edges
+    log-uniform 16-96 (seeded), u0 in [0.01, 0.08], tau in [0.55, 1.0]; one
+    persistent launch per step, 100-step graph replay, autotuned launch shape."""
+    import numpy as np
+    import torch
+
+    import paper_2307_11752_amd as P
+    from paper_2307_11752_amd import workloads as W
+
+    shapes, u0, taus = W.tgv_ensemble()
+    storage = args.storage or "f32"
+    shifted = bool(args.shifted) if args.shifted is not None else False
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    batch = P.Batch(1, shapes, taus, storage=storage, shifted=shifted, stream=stream)
+    fields = [W.tgv3d_velocity(*s, a) for s, a in zip(shapes, u0)]
+
+    def init():
+        for m, u in zip(batch, fields):
+            m.init_equilibrium(None, u)
+
+    init()
+    threads, bpc, tuned_ms = batch.autotune(trial_steps=10)
+    init()
+    if args.graph_steps:
+        batch.set_graph_steps(args.graph_steps)
+    cells = sum(int(np.prod(s)) for s in shapes)
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build(force=False)
+        done_cells, done, t0 = 0, [], time.perf_counter()
+        refs = {}
+        for l, (s, t, u) in enumerate(zip(shapes, taus, fields)):
+            nx, ny, nz = s
+            r = oracle.Lattice(1, np.ones((nz, ny, nx), np.uint8), 7, t)
+            r.init_equilibrium(None, u)
+            ts = time.perf_counter()
+            r.step(2)
+            done_cells += 2 * nx * ny * nz
+            refs[l] = (r, time.perf_counter() - ts)
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        el = sum(v[1] for v in refs.values())
+        cpu = {"value": round(done_cells / el / 1e6, 3), "unit": "MLUPS",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"2 steps of each of the first {len(refs)} of {len(shapes)} ensemble "
+                         f"lattices ({done_cells // 2} cells, {el:.1f} s of stepping)"}
+        batch.step(2)
+        errs = []
+        for l, (r, _) in refs.items():
+            _, u_g = batch[l].moments()
+            _, u_o = r.moments()
+            u_g = u_g.cpu().numpy()
+            errs.append(np.linalg.norm(u_g - u_o) / np.linalg.norm(u_o))
+        parity = {"steps": 2, "members_compared": len(refs), "u_rel_l2_max": float(max(errs))}
+        init()
+
+    batch.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    batch.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = ev0.elapsed_time(ev1) / max(args.steps, 1)
+    sb = STORE_BYTES[storage]
+    alg_bytes = cells * 2 * 19 * sb
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    mlups = cells * args.steps / wall / 1e6
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / max(args.steps, 1), 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if storage == "f64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "ensemble: 256 periodic D3Q19 BGK Taylor-Green lattices, edges "
+                               "log-uniform 16-96 (seed 1107), u0 U[0.01,0.08], tau U[0.55,1.0]",
+                   "lattices": len(shapes), "cells": cells,
+                   "storage": storage + ("-shifted" if shifted else ""),
+                   "launch": {"threads": threads, "blocks_per_cu": bpc,
+                              "autotune_ms_per_step": round(tuned_ms, 5)},
+                   "graph_steps": args.graph_steps},
+        "kernel_ms_per_step": round(kernel_ms, 5),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "kernel": f"batch_step_kernel<Q=19,{storage}>"},
+        "cpu_baseline": cpu,
+        "oracle_parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -120,6 +229,10 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md, 'More than one GPU'); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "ensemble":
+        bench_ensemble(args)
+        return
 
     import numpy as np
     import torch

@@ -74,9 +74,12 @@ typedef enum {
 } lbm_status;
 
 /* Sizes of the two caller-allocated device buffers for a lattice.
- * pop_bytes: q*N populations of the storage type (structure of arrays,
- * population i of cell idx at element i*N + idx).  aux_bytes: per-cell link
- * masks plus reduction scratch.  Host-only; needs no GPU. */
+ * pop_bytes: q population arrays of the storage type (structure of arrays:
+ * population i of cell idx at element i*PS + idx, where the stride PS is N
+ * rounded up to a multiple of 64 so every array starts on a 256-byte
+ * boundary; the value stored depends on the propagation phase, so read
+ * populations with lbm_get_populations).  aux_bytes: per-cell link masks
+ * plus reduction scratch.  Host-only; needs no GPU. */
 lbm_status lbm_required_bytes(lbm_descriptor d, int nx, int ny, int nz, lbm_storage s,
                               size_t* pop_bytes, size_t* aux_bytes);
 
@@ -163,8 +166,72 @@ lbm_status lbm_totals(lbm_lattice* h, double* mass, double momentum[3], double s
 /* Number of steps taken since the last initialisation, and fluid cell count. */
 lbm_status lbm_get_info(const lbm_lattice* h, long long* steps, long long* fluid_cells);
 
-/* Release the handle (not the caller's buffers).  Waits for its stream. */
+/* Release the handle (not the caller's buffers).  Waits for its stream.
+ * Lattices owned by a batch are released with the batch. */
 lbm_status lbm_lattice_destroy(lbm_lattice* h);
+
+/* ---------------------------------------------------------------------------
+ * Batched ensembles.  `count` fully fluid lattices, periodic on every axis,
+ * of uneven shapes dims[3*l .. 3*l+2] = (nx, ny, nz) and relaxation times
+ * tau[l], share one population buffer and one aux buffer (both caller-owned,
+ * sized by lbm_batch_required_bytes) and advance together: each time step is
+ * ONE persistent launch that walks a work list of (lattice, cell range)
+ * items, and runs of steps replay as a captured HIP graph.  The update of
+ * every cell is the single-lattice collide-and-stream (same kernels' cell
+ * arithmetic, same in-place AA layout).  No body force, no walls.
+ *
+ * Each member is also an ordinary lattice handle (lbm_batch_lattice): use
+ * lbm_init_equilibrium / lbm_set_populations / lbm_get_populations /
+ * lbm_moments / lbm_totals / lbm_get_info on it.  Calls that would advance
+ * or reconfigure a member alone (lbm_step, lbm_set_geometry, lbm_set_tau,
+ * lbm_set_body_force, lbm_set_wall_velocity, lbm_set_graph_steps,
+ * lbm_lattice_destroy) return LBM_ERR_STATE.  Nearest guide analogue: many
+ * cuboids (block lattices) per process (Core Concepts, "(Super,Block)Lattice").
+ * ------------------------------------------------------------------------- */
+typedef struct lbm_batch lbm_batch; /* opaque handle */
+
+/* Host-only sizes of the batch's population and aux buffers. */
+lbm_status lbm_batch_required_bytes(lbm_descriptor d, int count, const int* dims, lbm_storage s,
+                                    size_t* pop_bytes, size_t* aux_bytes);
+
+/* Create the batch on the current device (sync: uploads the all-fluid
+ * geometry of every member).  Arguments as lbm_lattice_create, per member. */
+lbm_status lbm_batch_create(lbm_batch** out, lbm_descriptor d, int count, const int* dims,
+                            const double* tau, lbm_storage s, unsigned flags, void* dev_pop,
+                            size_t pop_bytes, void* dev_aux, size_t aux_bytes, void* hip_stream);
+
+/* Borrow member `index` as a lattice handle (owned by the batch). */
+lbm_status lbm_batch_lattice(lbm_batch* b, int index, lbm_lattice** view);
+
+/* Advance every member by n steps.  async.  All members must be initialised
+ * and in the same propagation phase (LBM_ERR_STATE otherwise). */
+lbm_status lbm_batch_step(lbm_batch* b, int n);
+
+/* As lbm_set_graph_steps, for the batch launch. */
+lbm_status lbm_batch_set_graph_steps(lbm_batch* b, int steps);
+
+/* Launch shape: threads per block (128, 256 or 512, at least the widest
+ * row's lanes; a phase-0 item is a run of that many lanes of cells, a
+ * phase-1 item as many whole x-rows as fit) and resident blocks per compute
+ * unit of the persistent grid (1..64), or 0 for one block per work item. */
+lbm_status lbm_batch_set_launch(lbm_batch* b, int threads, int blocks_per_cu);
+
+/* Measure every launch shape in the built-in candidate set (threads 128 /
+ * 256 / 512 x blocks per CU 0 / 2 / 4 / 8 / 16) over trial_steps (even) timed
+ * steps each, keep the fastest, and report it.  Members must be initialised
+ * (any state will do); every candidate advances them by trial_steps + 2
+ * steps (the propagation phase is kept), so initialise them again afterwards.
+ * sync. */
+lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* threads, int* blocks_per_cu,
+                              double* best_ms_per_step);
+
+lbm_status lbm_batch_get_info(const lbm_batch* b, int* count, long long* total_cells,
+                              int* threads, int* blocks_per_cu);
+
+/* Release the batch and its member handles (not the caller's buffers). */
+lbm_status lbm_batch_destroy(lbm_batch* b);
+
+const char* lbm_batch_last_error(const lbm_batch* b);
 
 const char* lbm_status_string(lbm_status st);
 /* Message of the last failed call on h ("" if none); h may be NULL for

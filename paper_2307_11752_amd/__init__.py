@@ -7,7 +7,7 @@ Guide, release 1.6 (arXiv:2307.11752).
 """
 from ._lib import (D2Q9, D3Q19, STORE_BF16, STORE_F16, STORE_F32, STORE_F64, LBMError)  # noqa: F401
 
-__all__ = ["Lattice", "D2Q9", "D3Q19", "STORE_F64", "STORE_F32", "STORE_F16", "STORE_BF16",
+__all__ = ["Lattice", "Batch", "D2Q9", "D3Q19", "STORE_F64", "STORE_F32", "STORE_F16", "STORE_BF16",
            "LBMError"]
 
 
@@ -16,4 +16,8 @@ def __getattr__(name):
         from .lattice import Lattice
 
         return Lattice
+    if name == "Batch":
+        from .batch import Batch
+
+        return Batch
     raise AttributeError(name)

@@ -38,6 +38,8 @@ _SZ = ctypes.c_size_t
 _PSZ = ctypes.POINTER(ctypes.c_size_t)
 _PP = ctypes.POINTER(ctypes.c_void_p)
 _PLL = ctypes.POINTER(ctypes.c_longlong)
+_PI = ctypes.POINTER(ctypes.c_int)
+_PD = ctypes.POINTER(ctypes.c_double)
 
 SIGNATURES = {
     "lbm_required_bytes": ([_I, _I, _I, _I, _I, _PSZ, _PSZ], _I),
@@ -58,6 +60,16 @@ SIGNATURES = {
     "lbm_lattice_destroy": ([_P], _I),
     "lbm_status_string": ([_I], ctypes.c_char_p),
     "lbm_last_error": ([_P], ctypes.c_char_p),
+    "lbm_batch_required_bytes": ([_I, _I, _P, _I, _PSZ, _PSZ], _I),
+    "lbm_batch_create": ([_PP, _I, _I, _P, _P, _I, _U, _P, _SZ, _P, _SZ, _P], _I),
+    "lbm_batch_lattice": ([_P, _I, _PP], _I),
+    "lbm_batch_step": ([_P, _I], _I),
+    "lbm_batch_set_graph_steps": ([_P, _I], _I),
+    "lbm_batch_set_launch": ([_P, _I, _I], _I),
+    "lbm_batch_autotune": ([_P, _I, _PI, _PI, _PD], _I),
+    "lbm_batch_get_info": ([_P, _PI, _PLL, _PI, _PI], _I),
+    "lbm_batch_destroy": ([_P], _I),
+    "lbm_batch_last_error": ([_P], ctypes.c_char_p),
 }
 
 _lib = None
@@ -91,5 +103,14 @@ def check(status, handle=None):
     if status != OK:
         lib = load()
         msg = lib.lbm_last_error(handle).decode() or lib.lbm_status_string(status).decode()
+        raise LBMError(status, msg)
+    return status
+
+
+def check_batch(status, batch):
+    if status != OK:
+        lib = load()
+        msg = lib.lbm_batch_last_error(batch).decode() or lib.lbm_last_error(None).decode() or \
+            lib.lbm_status_string(status).decode()
         raise LBMError(status, msg)
     return status

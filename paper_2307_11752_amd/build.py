@@ -8,8 +8,9 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", "lbm.hip")]
-DEPS = SRC + [os.path.join(HERE, "csrc", "lattice.hpp"), os.path.join(ROOT, "include", "lbm.h")]
+SRC = [os.path.join(HERE, "csrc", "lbm.hip"), os.path.join(HERE, "csrc", "batch.hip")]
+DEPS = SRC + [os.path.join(HERE, "csrc", "lattice.hpp"), os.path.join(HERE, "csrc", "handle.hpp"),
+               os.path.join(ROOT, "include", "lbm.h")]
 LIB = os.path.join(HERE, "liblbm_hip.so")
 ARCH = "gfx950"
 

@@ -1,0 +1,541 @@
+// batch.hip -- an ensemble of fully periodic lattices of uneven size, each with
+// its own relaxation time, advanced together: one persistent launch per time
+// step walks a work list of (lattice, cell range) items, and runs of steps
+// replay as one captured HIP graph.
+//
+// The per-cell update is the same fused BGK collide-and-stream as the single
+// lattice path (OpenLB User Guide 1.6, Introduction, collision and streaming
+// equations; Core Concepts, BGK listing), in the same in-place AA layout, so
+// every lattice of a batch is also an ordinary lattice handle (a view) whose
+// populations, moments and totals are read with the single-lattice calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fluid_path.hpp"
+#include "handle.hpp"
+#include "lattice.hpp"
+#include "lbm.h"
+
+using namespace lbm;
+using lbm_detail::fail;
+
+namespace {
+
+struct BatchLat {
+  uint64_t pop_off;  // element offset of the lattice's populations in the batch buffer
+  int nx, ny, nz;
+  uint32_t N, PS;  // cells, population stride
+  double omega;
+  int c;    // cells per lane: 8 bytes' worth when nx allows it, else 1
+  int tpr;  // lanes per x-row = nx / c
+};
+
+// A work item carries its lattice's parameters, so a block needs one scalar
+// load (no dependent second load) before it can address memory.
+struct BatchItem {
+  uint64_t pop_off;
+  double omega;
+  uint32_t N, PS;
+  int nx, ny, nz;
+  int c, tpr;
+  uint32_t first;  // phase 0: first cell; phase 1: first x-row
+  uint32_t count;  // phase 0: cells; phase 1: rows
+};
+
+// One launch advances every lattice of the batch by one step.  Items never
+// span two lattices, so a block's lattice (and its lane width) is uniform and
+// the barriers of the phase-1 row body are reached by the whole block.
+template <int Q, typename S, bool SHIFT, int PHASE>
+__global__ void __launch_bounds__(512)
+    batch_step_kernel(S* __restrict__ base, const BatchItem* __restrict__ items, int nitems) {
+  using T = typename Store<S>::T;
+  constexpr int CM = Pack8<S>::C;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  for (int it = (int)blockIdx.x; it < nitems; it += (int)gridDim.x) {
+    const BatchItem item = items[it];
+    const BatchItem& L = item;
+    StepParams<T> p{};
+    p.omega = (T)L.omega;
+    p.kguo = (T)(1.0 - 0.5 * L.omega);
+    S* pop = base + L.pop_off;
+    if (PHASE == 0) {
+      const uint32_t c0 = item.first + (uint32_t)L.c * threadIdx.x;
+      if (c0 < item.first + item.count) {
+        if (L.c == CM)
+          fluid_cells_p0<Q, S, SHIFT, CM>(pop, L.PS, c0, p);
+        else
+          fluid_cells_p0<Q, S, SHIFT, 1>(pop, L.PS, c0, p);
+      }
+    } else {
+      const int rloc = (int)threadIdx.x / L.tpr;
+      const int t = (int)threadIdx.x - rloc * L.tpr;
+      const bool active = rloc < (int)item.count;
+      const int row = (int)item.first + rloc;
+      S* tile = (S*)smem_raw + (size_t)rloc * Shifted<Q>::count() * L.nx;
+      if (L.c == CM)
+        fluid_rows_p1<Q, S, SHIFT, CM>(pop, L.nx, L.ny, L.nz, L.PS, row, active, t, tile, p);
+      else
+        fluid_rows_p1<Q, S, SHIFT, 1>(pop, L.nx, L.ny, L.nz, L.PS, row, active, t, tile, p);
+      __syncthreads();  // the next item reuses the LDS tile
+    }
+  }
+}
+
+template <int Q, typename S, bool SHIFT>
+void launch_batch(const void* base, const BatchItem* items, int nitems, int phase, int grid,
+                  int threads, hipStream_t stream) {
+  if (phase == 0) {
+    hipLaunchKernelGGL((batch_step_kernel<Q, S, SHIFT, 0>), dim3(grid), dim3(threads), 0, stream,
+                       (S*)base, items, nitems);
+  } else {
+    const size_t lds = (size_t)threads * Pack8<S>::C * Shifted<Q>::count() * sizeof(S);
+    hipLaunchKernelGGL((batch_step_kernel<Q, S, SHIFT, 1>), dim3(grid), dim3(threads), lds,
+                       stream, (S*)base, items, nitems);
+  }
+}
+
+using LaunchFn = void (*)(const void*, const BatchItem*, int, int, int, int, hipStream_t);
+
+template <int Q, bool SHIFT>
+LaunchFn launch_for_storage(int s) {
+  switch (s) {
+    case LBM_STORE_F64: return launch_batch<Q, double, SHIFT>;
+    case LBM_STORE_F32: return launch_batch<Q, float, SHIFT>;
+    case LBM_STORE_F16: return launch_batch<Q, _Float16, SHIFT>;
+    default: return launch_batch<Q, bf16s, SHIFT>;
+  }
+}
+
+LaunchFn launcher(int q, int storage, bool shifted) {
+  if (q == 9) return shifted ? launch_for_storage<9, true>(storage) : launch_for_storage<9, false>(storage);
+  return shifted ? launch_for_storage<19, true>(storage) : launch_for_storage<19, false>(storage);
+}
+
+constexpr int MIN_THREADS = 128;  // smallest block; sizes the phase-0 item table
+constexpr int MAX_THREADS = 512;
+const int THREAD_CHOICES[] = {128, 256, 512};
+// 0 = one block per item (the grid covers the whole work list); otherwise
+// that many resident blocks per compute unit loop over the items
+const int BLOCKS_PER_CU_CHOICES[] = {0, 2, 4, 8, 16};
+
+struct BatchLayout {
+  std::vector<size_t> pop_off, aux_off;  // bytes, per lattice
+  size_t pop_total = 0, items0_off = 0, items1_off = 0, aux_total = 0;
+  size_t max_items0 = 0, max_items1 = 0;
+};
+
+lbm_status batch_layout(lbm_descriptor d, int count, const int* dims, lbm_storage s,
+                        BatchLayout* L, std::string* why) {
+  if (count <= 0 || !dims) {
+    *why = "count must be positive and dims non-NULL";
+    return LBM_ERR_ARG;
+  }
+  L->pop_off.resize(count);
+  L->aux_off.resize(count);
+  size_t pop = 0, aux = 0, items0 = 0, items1 = 0;
+  for (int b = 0; b < count; ++b) {
+    size_t pb = 0, ab = 0;
+    lbm_status st = lbm_required_bytes(d, dims[3 * b], dims[3 * b + 1], dims[3 * b + 2], s, &pb, &ab);
+    if (st) {
+      *why = "lattice " + std::to_string(b) + ": " + lbm_last_error(nullptr);
+      return st;
+    }
+    L->pop_off[b] = pop;
+    L->aux_off[b] = aux;
+    pop += pb;  // each part is a multiple of 256 bytes
+    aux += ab;
+    const size_t N = (size_t)dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
+    const int cmax = 8 / (int)storage_bytes(s);
+    const int lanes = dims[3 * b] % cmax == 0 ? dims[3 * b] / cmax : dims[3 * b];
+    if (lanes > MAX_THREADS) {
+      *why = "lattice " + std::to_string(b) + ": an x-row needs " + std::to_string(lanes) +
+             " lanes, more than " + std::to_string(MAX_THREADS);
+      return LBM_ERR_UNSUPPORTED;
+    }
+    items0 += (N + MIN_THREADS - 1) / MIN_THREADS;  // at least one lane-cell per thread
+    items1 += (size_t)dims[3 * b + 1] * dims[3 * b + 2];  // at most one row per item
+  }
+  if (pop / storage_bytes(s) >= 4294967296.0) {
+    *why = "the batch's populations exceed 2^32 elements";
+    return LBM_ERR_UNSUPPORTED;
+  }
+  L->pop_total = pop;
+  L->items0_off = align256(aux);
+  L->items1_off = align256(L->items0_off + sizeof(BatchItem) * items0);
+  L->max_items0 = items0;
+  L->max_items1 = items1;
+  L->aux_total = align256(L->items1_off + sizeof(BatchItem) * items1);
+  return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_batch {
+  int desc = 0, q = 0, count = 0, storage = 0;
+  bool shifted = false;
+  unsigned char* pop = nullptr;
+  unsigned char* aux = nullptr;
+  hipStream_t stream = nullptr;
+  int device = 0, num_cu = 0;
+  BatchLayout lay;
+  std::vector<lbm_lattice*> views;
+  std::vector<BatchLat> lats;
+  long long total_cells = 0;
+  int threads = 256, blocks_per_cu = 8, nitems0 = 0, nitems1 = 0;
+  int max_tpr = 1;  // widest row in lanes: blocks need at least this many threads
+  int graph_steps = 0;
+  hipGraphExec_t graph = nullptr;
+  std::string err;
+};
+
+namespace {
+
+lbm_status bfail(lbm_batch* b, lbm_status st, const std::string& msg) {
+  if (b) b->err = msg;
+  return st;
+}
+
+#define BHIP_TRY(b, call)                                                               \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return bfail((b), LBM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+void drop_batch_graph(lbm_batch* b) {
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+}
+
+// Cut every lattice into phase-0 items (runs of threads * c cells) and
+// phase-1 items (as many whole x-rows as threads lanes hold).
+lbm_status build_items(lbm_batch* b, int threads) {
+  if (threads < b->max_tpr)
+    return bfail(b, LBM_ERR_ARG, "threads per block must cover the widest row (" +
+                                     std::to_string(b->max_tpr) + " lanes)");
+  std::vector<BatchItem> i0, i1;
+  i0.reserve(b->lay.max_items0);
+  i1.reserve(b->lay.max_items1);
+  for (int l = 0; l < b->count; ++l) {
+    const BatchLat& L = b->lats[l];
+    BatchItem it{L.pop_off, L.omega, L.N, L.PS, L.nx, L.ny, L.nz, L.c, L.tpr, 0, 0};
+    const uint32_t chunk = (uint32_t)threads * (uint32_t)L.c;
+    for (uint32_t c = 0; c < L.N; c += chunk) {
+      it.first = c;
+      it.count = std::min<uint32_t>(chunk, L.N - c);
+      i0.push_back(it);
+    }
+    const uint32_t rows = (uint32_t)L.ny * (uint32_t)L.nz;
+    const uint32_t per = (uint32_t)(threads / L.tpr);
+    for (uint32_t r = 0; r < rows; r += per) {
+      it.first = r;
+      it.count = std::min<uint32_t>(per, rows - r);
+      i1.push_back(it);
+    }
+  }
+  if (i0.size() > b->lay.max_items0 || i1.size() > b->lay.max_items1)
+    return bfail(b, LBM_ERR_ARG, "item table overflow");
+  BHIP_TRY(b, hipMemcpyAsync(b->aux + b->lay.items0_off, i0.data(), sizeof(BatchItem) * i0.size(),
+                             hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipMemcpyAsync(b->aux + b->lay.items1_off, i1.data(), sizeof(BatchItem) * i1.size(),
+                             hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  b->nitems0 = (int)i0.size();
+  b->nitems1 = (int)i1.size();
+  b->threads = threads;
+  drop_batch_graph(b);
+  return LBM_OK;
+}
+
+void launch_one(lbm_batch* b, int phase) {
+  const LaunchFn fn = launcher(b->q, b->storage, b->shifted);
+  const int n = phase == 0 ? b->nitems0 : b->nitems1;
+  const size_t off = phase == 0 ? b->lay.items0_off : b->lay.items1_off;
+  const int grid = b->blocks_per_cu == 0 ? std::max(1, n)
+                                         : std::max(1, std::min(n, b->blocks_per_cu * b->num_cu));
+  fn(b->pop, (const BatchItem*)(b->aux + off), n, phase, grid, b->threads, b->stream);
+}
+
+lbm_status benter(lbm_batch* b) {
+  if (!b) return LBM_ERR_ARG;
+  b->err.clear();
+  BHIP_TRY(b, hipSetDevice(b->device));
+  return LBM_OK;
+}
+
+// All views must be initialised and in the same propagation phase.
+lbm_status common_phase(lbm_batch* b, int* phase) {
+  for (int l = 0; l < b->count; ++l) {
+    const lbm_lattice* v = b->views[l];
+    if (!v->initialized)
+      return bfail(b, LBM_ERR_STATE, "lattice " + std::to_string(l) + " is not initialised");
+    if (v->phase != b->views[0]->phase)
+      return bfail(b, LBM_ERR_STATE, "lattices are in different propagation phases");
+  }
+  *phase = b->views[0]->phase;
+  return LBM_OK;
+}
+
+void advance_views(lbm_batch* b, int n) {
+  for (lbm_lattice* v : b->views) {
+    v->phase ^= (n & 1);
+    v->steps += n;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_batch_required_bytes(lbm_descriptor d, int count, const int* dims, lbm_storage s,
+                                    size_t* pop_bytes, size_t* aux_bytes) {
+  BatchLayout L;
+  std::string why;
+  lbm_status st = batch_layout(d, count, dims, s, &L, &why);
+  if (st) return lbm_detail::fail(nullptr, st, why);
+  if (pop_bytes) *pop_bytes = L.pop_total;
+  if (aux_bytes) *aux_bytes = L.aux_total;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_create(lbm_batch** out, lbm_descriptor d, int count, const int* dims,
+                            const double* tau, lbm_storage s, unsigned flags, void* dev_pop,
+                            size_t pop_bytes, void* dev_aux, size_t aux_bytes, void* hip_stream) {
+  if (!out) return lbm_detail::fail(nullptr, LBM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  BatchLayout L;
+  std::string why;
+  lbm_status st = batch_layout(d, count, dims, s, &L, &why);
+  if (st) return lbm_detail::fail(nullptr, st, why);
+  if (!tau) return lbm_detail::fail(nullptr, LBM_ERR_ARG, "tau is NULL");
+  if (!dev_pop || !dev_aux) return lbm_detail::fail(nullptr, LBM_ERR_ARG, "device buffers must not be NULL");
+  if (pop_bytes < L.pop_total || aux_bytes < L.aux_total)
+    return lbm_detail::fail(nullptr, LBM_ERR_ARG, "buffers smaller than lbm_batch_required_bytes");
+  if (((uintptr_t)dev_pop & 255u) || ((uintptr_t)dev_aux & 255u))
+    return lbm_detail::fail(nullptr, LBM_ERR_ARG, "device buffers must be 256-byte aligned");
+  lbm_batch* b = new (std::nothrow) lbm_batch();
+  if (!b) return lbm_detail::fail(nullptr, LBM_ERR_ARG, "out of host memory");
+  b->desc = d;
+  b->q = qof(d);
+  b->count = count;
+  b->storage = s;
+  b->shifted = (flags & LBM_FLAG_SHIFTED) != 0;
+  b->pop = (unsigned char*)dev_pop;
+  b->aux = (unsigned char*)dev_aux;
+  b->stream = (hipStream_t)hip_stream;
+  b->lay = L;
+  auto undo = [&](lbm_status code, const std::string& msg) {
+    for (lbm_lattice* v : b->views) {
+      v->batch = nullptr;
+      lbm_lattice_destroy(v);
+    }
+    delete b;
+    return lbm_detail::fail(nullptr, code, msg);
+  };
+  if (hipGetDevice(&b->device) != hipSuccess) return undo(LBM_ERR_HIP, "hipGetDevice failed");
+  if (hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, b->device) !=
+      hipSuccess)
+    return undo(LBM_ERR_HIP, "hipDeviceGetAttribute failed");
+  std::vector<uint8_t> mat;
+  for (int l = 0; l < count; ++l) {
+    const int nx = dims[3 * l], ny = dims[3 * l + 1], nz = dims[3 * l + 2];
+    lbm_lattice* v = nullptr;
+    size_t pb = 0, ab = 0;
+    lbm_required_bytes(d, nx, ny, nz, s, &pb, &ab);
+    st = lbm_lattice_create(&v, d, nx, ny, nz, tau[l], s, flags, b->pop + L.pop_off[l], pb,
+                            b->aux + L.aux_off[l], ab, hip_stream);
+    if (st) return undo(st, "lattice " + std::to_string(l) + ": " + lbm_last_error(nullptr));
+    b->views.push_back(v);
+    mat.assign((size_t)nx * ny * nz, 1);  // fully fluid, periodic on every axis
+    st = lbm_set_geometry(v, mat.data(), d == LBM_D2Q9 ? 3u : 7u);
+    if (st) return undo(st, "lattice " + std::to_string(l) + ": " + lbm_last_error(v));
+    v->batch = b;
+    BatchLat bl;
+    bl.pop_off = L.pop_off[l] / storage_bytes(s);
+    bl.nx = nx;
+    bl.ny = ny;
+    bl.nz = nz;
+    bl.N = (uint32_t)v->N;
+    bl.PS = (uint32_t)v->ps;
+    bl.omega = v->omega;
+    const int cmax = 8 / (int)storage_bytes(s);
+    bl.c = nx % cmax == 0 ? cmax : 1;
+    bl.tpr = nx / bl.c;
+    b->max_tpr = std::max(b->max_tpr, bl.tpr);
+    b->lats.push_back(bl);
+    b->total_cells += (long long)v->N;
+  }
+  int t0 = 128;
+  while (t0 < b->max_tpr) t0 *= 2;
+  st = build_items(b, std::max(256, t0));
+  if (st) return undo(st, b->err);
+  *out = b;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_lattice(lbm_batch* b, int index, lbm_lattice** view) {
+  if (!b || !view) return LBM_ERR_ARG;
+  if (index < 0 || index >= b->count) return bfail(b, LBM_ERR_ARG, "index out of range");
+  *view = b->views[index];
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_launch(lbm_batch* b, int threads, int blocks_per_cu) {
+  lbm_status st = benter(b);
+  if (st) return st;
+  bool ok = false;
+  for (int t : THREAD_CHOICES) ok |= t == threads;
+  if (!ok) return bfail(b, LBM_ERR_ARG, "threads must be 128, 256 or 512");
+  if (blocks_per_cu < 0 || blocks_per_cu > 64)
+    return bfail(b, LBM_ERR_ARG, "blocks_per_cu in 0..64 (0 = one block per work item)");
+  b->blocks_per_cu = blocks_per_cu;
+  if (threads != b->threads) return build_items(b, threads);
+  drop_batch_graph(b);
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch* b, int n) {
+  lbm_status st = benter(b);
+  if (st) return st;
+  if (n < 0) return bfail(b, LBM_ERR_ARG, "n must be >= 0");
+  int phase = 0;
+  st = common_phase(b, &phase);
+  if (st) return st;
+  int left = n;
+  if (b->graph_steps > 0 && n >= b->graph_steps) {
+    if (phase != 0) {
+      launch_one(b, 1);
+      phase = 0;
+      --left;
+    }
+    if (!b->graph && left >= b->graph_steps) {
+      hipGraph_t g = nullptr;
+      BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      for (int s = 0; s < b->graph_steps; ++s) launch_one(b, s & 1);
+      hipError_t e = hipStreamEndCapture(b->stream, &g);
+      if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return bfail(b, LBM_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      }
+      e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        b->graph = nullptr;
+        return bfail(b, LBM_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      }
+    }
+    while (b->graph && left >= b->graph_steps) {
+      BHIP_TRY(b, hipGraphLaunch(b->graph, b->stream));
+      left -= b->graph_steps;
+    }
+  }
+  for (int s = 0; s < left; ++s) {
+    launch_one(b, phase);
+    phase ^= 1;
+  }
+  advance_views(b, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return bfail(b, LBM_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_graph_steps(lbm_batch* b, int steps) {
+  lbm_status st = benter(b);
+  if (st) return st;
+  if (steps < 0 || (steps & 1)) return bfail(b, LBM_ERR_ARG, "graph length must be even and >= 0");
+  if (steps > 0 && b->stream == nullptr)
+    return bfail(b, LBM_ERR_ARG, "graph replay needs a created (non-null) stream");
+  drop_batch_graph(b);
+  b->graph_steps = steps;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* threads, int* blocks_per_cu,
+                              double* best_ms_per_step) {
+  lbm_status st = benter(b);
+  if (st) return st;
+  if (trial_steps < 2 || (trial_steps & 1)) return bfail(b, LBM_ERR_ARG, "trial_steps must be even and >= 2");
+  int phase = 0;
+  st = common_phase(b, &phase);
+  if (st) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BHIP_TRY(b, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return bfail(b, LBM_ERR_HIP, "hipEventCreate failed");
+  }
+  double best = 1e300;
+  int best_t = b->threads, best_b = b->blocks_per_cu;
+  lbm_status result = LBM_OK;
+  for (int t : THREAD_CHOICES) {
+    if (t < b->max_tpr) continue;
+    if ((result = build_items(b, t)) != LBM_OK) break;
+    for (int bpc : BLOCKS_PER_CU_CHOICES) {
+      b->blocks_per_cu = bpc;
+      // two untimed steps, then the timed trial; every trial has an even
+      // length, so the propagation phase is unchanged
+      launch_one(b, phase);
+      launch_one(b, phase ^ 1);
+      (void)hipEventRecord(e0, b->stream);
+      for (int s = 0; s < trial_steps; ++s) launch_one(b, phase ^ (s & 1));
+      (void)hipEventRecord(e1, b->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        result = bfail(b, LBM_ERR_HIP, "autotune trial failed");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      advance_views(b, trial_steps + 2);
+      if (ms / trial_steps < best) {
+        best = ms / trial_steps;
+        best_t = t;
+        best_b = bpc;
+      }
+    }
+    if (result != LBM_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (result != LBM_OK) return result;
+  b->blocks_per_cu = best_b;
+  st = build_items(b, best_t);
+  if (st) return st;
+  if (threads) *threads = best_t;
+  if (blocks_per_cu) *blocks_per_cu = best_b;
+  if (best_ms_per_step) *best_ms_per_step = best;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_get_info(const lbm_batch* b, int* count, long long* total_cells,
+                              int* threads, int* blocks_per_cu) {
+  if (!b) return LBM_ERR_ARG;
+  if (count) *count = b->count;
+  if (total_cells) *total_cells = b->total_cells;
+  if (threads) *threads = b->threads;
+  if (blocks_per_cu) *blocks_per_cu = b->blocks_per_cu;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return LBM_ERR_ARG;
+  hipError_t e = hipSetDevice(b->device);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  drop_batch_graph(b);
+  for (lbm_lattice* v : b->views) {
+    v->batch = nullptr;
+    lbm_lattice_destroy(v);
+  }
+  delete b;
+  return e == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : ""; }
+
+}  // extern "C"

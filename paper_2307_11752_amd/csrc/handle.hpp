@@ -1,0 +1,98 @@
+// handle.hpp -- host-side state of a lattice handle, shared by the C ABI
+// implementation (lbm.hip) and the batched ensemble (batch.hip).  Internal:
+// not part of the installed interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "lbm.h"
+
+constexpr int RED_BLOCKS = 1024;
+constexpr int RED_THREADS = 256;
+constexpr int RED_FIELDS = 8;  // mass, jx, jy, jz, sum|u|^2, max|u|, fluid count, spare
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct AuxLayout {
+  size_t link, mov, partials, result, total;
+};
+
+inline AuxLayout aux_layout(size_t N) {
+  AuxLayout a;
+  a.link = 0;
+  a.mov = align256(a.link + 4 * N);
+  a.partials = align256(a.mov + 4 * N);
+  a.result = align256(a.partials + sizeof(double) * RED_BLOCKS * RED_FIELDS);
+  a.total = align256(a.result + sizeof(double) * RED_FIELDS);
+  return a;
+}
+
+inline int qof(int d) { return d == LBM_D2Q9 ? 9 : 19; }
+
+// Distance in elements between consecutive population arrays: N rounded up to
+// 64 elements, so that every array starts on a 256-byte boundary whatever N is.
+inline size_t pop_stride(size_t N) { return (N + 63) & ~size_t(63); }
+
+inline size_t storage_bytes(int s) {
+  switch (s) {
+    case LBM_STORE_F64: return 8;
+    case LBM_STORE_F32: return 4;
+    case LBM_STORE_F16: return 2;
+    case LBM_STORE_BF16: return 2;
+  }
+  return 0;
+}
+
+
+// ---------------------------------------------------------------------------
+// Handle
+// ---------------------------------------------------------------------------
+struct lbm_lattice {
+  int desc = 0, q = 0, nx = 0, ny = 0, nz = 0;
+  size_t N = 0;
+  size_t ps = 0;  // population stride in elements (pop_stride(N))
+  int storage = 0;
+  bool shifted = false;
+  double tau = 0.0, omega = 0.0;
+  double g[3] = {0, 0, 0}, uw[3] = {0, 0, 0};
+  void* pop = nullptr;
+  size_t pop_bytes = 0;
+  unsigned char* aux = nullptr;
+  size_t aux_bytes = 0;
+  AuxLayout lay{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool has_geometry = false, initialized = false, all_fluid = false, has_moving_cells = false;
+  unsigned periodic = 0;
+  int phase = 0;
+  long long steps = 0;
+  long long nfluid = 0;
+  int bx = 256, nxb = 1;
+  // Replay of a captured run of graph_steps steps (0 = direct launches).  The
+  // graph bakes in the kernel arguments, so any parameter change drops it.
+  int graph_steps = 0;
+  hipGraphExec_t graph = nullptr;
+  // Non-null for a lattice owned by a batch (lbm_batch_lattice): the batch
+  // advances it, and calls that would change what the batch launch assumes
+  // are refused.
+  const void* batch = nullptr;
+  std::string err;
+};
+
+
+namespace lbm_detail {
+lbm_status fail(lbm_lattice* h, lbm_status st, const std::string& msg);
+void drop_graph(lbm_lattice* h);
+}  // namespace lbm_detail
+
+#define HIP_TRY(h, call)                                                                  \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return lbm_detail::fail((h), LBM_ERR_HIP,                                           \
+                              std::string(#call) + ": " + hipGetErrorString(e_));         \
+  } while (0)

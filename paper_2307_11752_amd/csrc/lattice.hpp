@@ -215,4 +215,30 @@ __device__ __forceinline__ T collide(T (&f)[Q], const StepParams<T>& p) {
   return rho;
 }
 
+// ---------------------------------------------------------------------------
+// Neighbour addressing.  Coordinates wrap on every axis; on non-periodic axes
+// fluid cells never sit on the edge, so the wrap is never taken there.
+// ---------------------------------------------------------------------------
+struct Nbr {
+  int X[3];
+  uint32_t R[3][3];  // R[dy+1][dz+1] = nx*(y' + ny*z')
+  __device__ __forceinline__ uint32_t at(int dx, int dy, int dz) const {
+    return (uint32_t)X[dx + 1] + R[dy + 1][dz + 1];
+  }
+};
+
+__device__ __forceinline__ Nbr make_nbr(int x, int y, int z, int nx, int ny, int nz) {
+  Nbr n;
+  n.X[0] = x == 0 ? nx - 1 : x - 1;
+  n.X[1] = x;
+  n.X[2] = x == nx - 1 ? 0 : x + 1;
+  const int Y[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
+  const int Z[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) n.R[a][b] = (uint32_t)nx * (uint32_t)(Y[a] + ny * Z[b]);
+  return n;
+}
+
 }  // namespace lbm

@@ -30,70 +30,14 @@
 #include <string>
 #include <vector>
 
+#include "handle.hpp"
+#include "fluid_path.hpp"
 #include "lattice.hpp"
 #include "lbm.h"
 
 using namespace lbm;
 
 namespace {
-
-constexpr int RED_BLOCKS = 1024;
-constexpr int RED_THREADS = 256;
-constexpr int RED_FIELDS = 8;  // mass, jx, jy, jz, sum|u|^2, max|u|, fluid count, spare
-
-inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
-
-struct AuxLayout {
-  size_t link, mov, partials, result, total;
-};
-
-inline AuxLayout aux_layout(size_t N) {
-  AuxLayout a;
-  a.link = 0;
-  a.mov = align256(a.link + 4 * N);
-  a.partials = align256(a.mov + 4 * N);
-  a.result = align256(a.partials + sizeof(double) * RED_BLOCKS * RED_FIELDS);
-  a.total = align256(a.result + sizeof(double) * RED_FIELDS);
-  return a;
-}
-
-inline int qof(int d) { return d == LBM_D2Q9 ? 9 : 19; }
-
-inline size_t storage_bytes(int s) {
-  switch (s) {
-    case LBM_STORE_F64: return 8;
-    case LBM_STORE_F32: return 4;
-    case LBM_STORE_F16: return 2;
-    case LBM_STORE_BF16: return 2;
-  }
-  return 0;
-}
-
-// ---------------------------------------------------------------------------
-// Neighbour addressing.  Coordinates wrap on every axis; on non-periodic axes
-// fluid cells never sit on the edge, so the wrap is never taken there.
-// ---------------------------------------------------------------------------
-struct Nbr {
-  int X[3];
-  uint32_t R[3][3];  // R[dy+1][dz+1] = nx*(y' + ny*z')
-  __device__ __forceinline__ uint32_t at(int dx, int dy, int dz) const {
-    return (uint32_t)X[dx + 1] + R[dy + 1][dz + 1];
-  }
-};
-
-__device__ __forceinline__ Nbr make_nbr(int x, int y, int z, int nx, int ny, int nz) {
-  Nbr n;
-  n.X[0] = x == 0 ? nx - 1 : x - 1;
-  n.X[1] = x;
-  n.X[2] = x == nx - 1 ? 0 : x + 1;
-  const int Y[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
-  const int Z[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) n.R[a][b] = (uint32_t)nx * (uint32_t)(Y[a] + ny * Z[b]);
-  return n;
-}
 
 // ---------------------------------------------------------------------------
 // The fused step kernel.  One thread per cell; a block covers a run of up to
@@ -189,143 +133,27 @@ __global__ void __launch_bounds__(256)
 // LDS and stored aligned.  This removes the misaligned accesses that
 // otherwise cost about 12 % of bandwidth in this phase.
 // ---------------------------------------------------------------------------
-typedef uint32_t raw8 __attribute__((ext_vector_type(2)));
-
-template <typename S>
-struct Pack8 {
-  static constexpr int C = 8 / (int)sizeof(S);
-  static __device__ __forceinline__ void unpack(raw8 r, S (&v)[C]) { __builtin_memcpy(v, &r, 8); }
-  static __device__ __forceinline__ raw8 pack(const S (&v)[C]) {
-    raw8 r;
-    __builtin_memcpy(&r, v, 8);
-    return r;
-  }
-};
-
-template <int Q>
-struct Shifted {
-  // number of velocities with c_x != 0, and the rank of velocity i among them
-  static constexpr int count() {
-    int n = 0;
-    for (int i = 0; i < Q; ++i) n += Vel<Q>::cx[i] != 0;
-    return n;
-  }
-  static constexpr int rank(int i) {
-    int n = 0;
-    for (int k = 0; k < i; ++k) n += Vel<Q>::cx[k] != 0;
-    return n;
-  }
-};
-
 template <int Q, typename S, bool SHIFT>
 __global__ void __launch_bounds__(256)
-    step_p0_flat_kernel(S* __restrict__ pop, uint32_t N, StepParams<typename Store<S>::T> p) {
-  using T = typename Store<S>::T;
-  using V = Vel<Q>;
+    step_p0_flat_kernel(S* __restrict__ pop, uint32_t N, uint32_t PS,
+                        StepParams<typename Store<S>::T> p) {
   constexpr int C = Pack8<S>::C;
   const uint32_t c0 = (uint32_t)C * (blockIdx.x * blockDim.x + threadIdx.x);
   if (c0 >= N) return;
-  S sv[Q][C];
-#pragma unroll
-  for (int i = 0; i < Q; ++i)
-    Pack8<S>::unpack(__builtin_nontemporal_load((const raw8*)(pop + (uint32_t)i * N + c0)), sv[i]);
-#pragma unroll
-  for (int k = 0; k < C; ++k) {
-    T f[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = Store<S>::cvt(sv[i][k]);
-    collide<Q, SHIFT, T>(f, p);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) sv[V::opp[i]][k] = Store<S>::pack(f[i]);
-  }
-#pragma unroll
-  for (int i = 0; i < Q; ++i)
-    __builtin_nontemporal_store(Pack8<S>::pack(sv[i]), (raw8*)(pop + (uint32_t)i * N + c0));
+  fluid_cells_p0<Q, S, SHIFT, C>(pop, PS, c0, p);
 }
 
 template <int Q, typename S, bool SHIFT>
 __global__ void __launch_bounds__(256)
     step_p1_rows_kernel(S* __restrict__ pop, int nx, int ny, int nz, uint32_t N, int tpr,
                         int rows_per_block, StepParams<typename Store<S>::T> p) {
-  using T = typename Store<S>::T;
-  using V = Vel<Q>;
   constexpr int C = Pack8<S>::C;
-  constexpr int NS = Shifted<Q>::count();
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int rloc = (int)threadIdx.x / tpr;
   const int t = (int)threadIdx.x - rloc * tpr;
   const int row = (int)blockIdx.x * rows_per_block + rloc;
-  const bool active = row < ny * nz;
-  S* tile = (S*)smem_raw + (size_t)rloc * NS * nx;
-  const int y = active ? row % ny : 0;
-  const int z = active ? row / ny : 0;
-  const int Y[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
-  const int Z[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
-  const int x0 = C * t;
-
-  S sv[Q][C];
-  if (active) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const int o = V::opp[i];
-      const uint32_t base = (uint32_t)o * N + (uint32_t)nx * (uint32_t)(Y[1 - V::cy[i]] + ny * Z[1 - V::cz[i]]);
-      const raw8 r = __builtin_nontemporal_load((const raw8*)(pop + base + x0));
-      if (V::cx[i] == 0) {
-        Pack8<S>::unpack(r, sv[i]);
-      } else {
-        *(raw8*)(tile + Shifted<Q>::rank(i) * nx + x0) = r;
-      }
-    }
-  }
-  __syncthreads();
-  if (active) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      if (V::cx[i] == 0) continue;
-#pragma unroll
-      for (int k = 0; k < C; ++k) {
-        int xs = x0 + k - V::cx[i];
-        xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-        sv[i][k] = tile[Shifted<Q>::rank(i) * nx + xs];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-      T f[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) f[i] = Store<S>::cvt(sv[i][k]);
-      collide<Q, SHIFT, T>(f, p);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) sv[i][k] = Store<S>::pack(f[i]);
-    }
-  }
-  __syncthreads();
-  if (active) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      if (V::cx[i] == 0) {
-        const uint32_t base = (uint32_t)i * N + (uint32_t)nx * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]);
-        __builtin_nontemporal_store(Pack8<S>::pack(sv[i]), (raw8*)(pop + base + x0));
-      } else {
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-          int xd = x0 + k + V::cx[i];
-          xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
-          tile[Shifted<Q>::rank(i) * nx + xd] = sv[i][k];
-        }
-      }
-    }
-  }
-  __syncthreads();
-  if (active) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      if (V::cx[i] == 0) continue;
-      const uint32_t base = (uint32_t)i * N + (uint32_t)nx * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]);
-      __builtin_nontemporal_store(*(const raw8*)(tile + Shifted<Q>::rank(i) * nx + x0),
-                                  (raw8*)(pop + base + x0));
-    }
-  }
+  S* tile = (S*)smem_raw + (size_t)rloc * Shifted<Q>::count() * nx;
+  fluid_rows_p1<Q, S, SHIFT, C>(pop, nx, ny, nz, N, row, row < ny * nz, t, tile, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -360,7 +188,7 @@ struct LinkVec {
 template <int Q, typename S, bool SHIFT>
 __global__ void __launch_bounds__(256)
     step_p0_masked_kernel(S* __restrict__ pop, const uint32_t* __restrict__ link,
-                          const uint32_t* __restrict__ mov, uint32_t N,
+                          const uint32_t* __restrict__ mov, uint32_t N, uint32_t PS,
                           StepParams<typename Store<S>::T> p) {
   using T = typename Store<S>::T;
   using V = Vel<Q>;
@@ -374,7 +202,7 @@ __global__ void __launch_bounds__(256)
   S sv[Q][C];
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    Pack8<S>::unpack(__builtin_nontemporal_load((const raw8*)(pop + (uint32_t)i * N + c0)), sv[i]);
+    Pack8<S>::unpack(__builtin_nontemporal_load((const raw8*)(pop + (uint32_t)i * PS + c0)), sv[i]);
 #pragma unroll
   for (int k = 0; k < C; ++k) {
     if (!(lw[k] & LINK_FLUID)) continue;
@@ -392,7 +220,7 @@ __global__ void __launch_bounds__(256)
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    __builtin_nontemporal_store(Pack8<S>::pack(sv[i]), (raw8*)(pop + (uint32_t)i * N + c0));
+    __builtin_nontemporal_store(Pack8<S>::pack(sv[i]), (raw8*)(pop + (uint32_t)i * PS + c0));
 }
 
 // ---------------------------------------------------------------------------
@@ -400,12 +228,12 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 template <int Q, typename S>
 __device__ __forceinline__ S load_phase(const S* pop, uint32_t lw, int i, uint32_t idx,
-                                        const Nbr& nb, int phase, uint32_t N) {
+                                        const Nbr& nb, int phase, uint32_t PS) {
   using V = Vel<Q>;
-  if (phase == 0 || i == 0) return pop[(uint32_t)i * N + idx];
+  if (phase == 0 || i == 0) return pop[(uint32_t)i * PS + idx];
   const int o = V::opp[i];
-  if ((lw >> (o - 1)) & 1u) return pop[(uint32_t)i * N + idx];
-  return pop[(uint32_t)o * N + nb.at(-V::cx[i], -V::cy[i], -V::cz[i])];
+  if ((lw >> (o - 1)) & 1u) return pop[(uint32_t)i * PS + idx];
+  return pop[(uint32_t)o * PS + nb.at(-V::cx[i], -V::cy[i], -V::cz[i])];
 }
 
 __device__ __forceinline__ void cell_coords(uint32_t idx, int nx, int ny, int& x, int& y, int& z) {
@@ -419,7 +247,7 @@ __device__ __forceinline__ void cell_coords(uint32_t idx, int nx, int ny, int& x
 template <int Q, typename S, bool SHIFT>
 __global__ void get_pop_kernel(const S* __restrict__ pop, const uint32_t* __restrict__ link,
                                double* __restrict__ out, int nx, int ny, int nz, uint32_t N,
-                               int phase) {
+                               uint32_t PS, int phase) {
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
        idx += gridDim.x * blockDim.x) {
     const uint32_t lw = link[idx];
@@ -430,7 +258,7 @@ __global__ void get_pop_kernel(const S* __restrict__ pop, const uint32_t* __rest
     for (int i = 0; i < Q; ++i) {
       double v = 0.0;
       if (lw & LINK_FLUID) {
-        v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, N));
+        v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, PS));
         if (SHIFT) v += weight<Q, double>(i);
       }
       out[(size_t)i * N + idx] = v;
@@ -440,14 +268,15 @@ __global__ void get_pop_kernel(const S* __restrict__ pop, const uint32_t* __rest
 
 // Populations from double natural layout; phase becomes 0.
 template <int Q, typename S, bool SHIFT>
-__global__ void set_pop_kernel(S* __restrict__ pop, const double* __restrict__ in, uint32_t N) {
+__global__ void set_pop_kernel(S* __restrict__ pop, const double* __restrict__ in, uint32_t N,
+                               uint32_t PS) {
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
        idx += gridDim.x * blockDim.x) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       double v = in[(size_t)i * N + idx];
       if (SHIFT) v -= weight<Q, double>(i);
-      pop[(size_t)i * N + idx] = Store<S>::from_f64(v);
+      pop[(size_t)i * PS + idx] = Store<S>::from_f64(v);
     }
   }
 }
@@ -456,7 +285,7 @@ __global__ void set_pop_kernel(S* __restrict__ pop, const double* __restrict__ i
 template <int Q, typename S, bool SHIFT>
 __global__ void init_eq_kernel(S* __restrict__ pop, const uint32_t* __restrict__ link,
                                const double* __restrict__ rho_in, const double* __restrict__ u_in,
-                               uint32_t N) {
+                               uint32_t N, uint32_t PS) {
   using V = Vel<Q>;
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
        idx += gridDim.x * blockDim.x) {
@@ -472,7 +301,7 @@ __global__ void init_eq_kernel(S* __restrict__ pop, const uint32_t* __restrict__
       const double cu = V::cx[i] * u[0] + V::cy[i] * u[1] + V::cz[i] * u[2];
       double feq = w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
       if (SHIFT) feq -= w;
-      pop[(size_t)i * N + idx] = Store<S>::from_f64(fluid ? feq : 0.0);
+      pop[(size_t)i * PS + idx] = Store<S>::from_f64(fluid ? feq : 0.0);
     }
   }
 }
@@ -481,8 +310,8 @@ __global__ void init_eq_kernel(S* __restrict__ pop, const uint32_t* __restrict__
 template <int Q, typename S, bool SHIFT>
 __global__ void moments_kernel(const S* __restrict__ pop, const uint32_t* __restrict__ link,
                                double* __restrict__ rho_out, double* __restrict__ u_out, int nx,
-                               int ny, int nz, uint32_t N, int phase, double gx, double gy,
-                               double gz) {
+                               int ny, int nz, uint32_t N, uint32_t PS, int phase, double gx,
+                               double gy, double gz) {
   using V = Vel<Q>;
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
        idx += gridDim.x * blockDim.x) {
@@ -495,7 +324,7 @@ __global__ void moments_kernel(const S* __restrict__ pop, const uint32_t* __rest
       double sf = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const double v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, N));
+        const double v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, PS));
         sf += v;
         j[0] += V::cx[i] * v;
         j[1] += V::cy[i] * v;
@@ -521,7 +350,7 @@ template <int Q, typename S, bool SHIFT>
 __global__ void __launch_bounds__(RED_THREADS)
     totals_partial_kernel(const S* __restrict__ pop, const uint32_t* __restrict__ link,
                           double* __restrict__ partials, int nx, int ny, int nz, uint32_t N,
-                          int phase, double gx, double gy, double gz) {
+                          uint32_t PS, int phase, double gx, double gy, double gz) {
   using V = Vel<Q>;
   double acc[RED_FIELDS] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
@@ -534,7 +363,7 @@ __global__ void __launch_bounds__(RED_THREADS)
     double sf = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const double v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, N));
+      const double v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, PS));
       sf += v;
       j[0] += V::cx[i] * v;
       j[1] += V::cy[i] * v;
@@ -604,37 +433,7 @@ __global__ void __launch_bounds__(RED_THREADS)
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// Handle
-// ---------------------------------------------------------------------------
-struct lbm_lattice {
-  int desc = 0, q = 0, nx = 0, ny = 0, nz = 0;
-  size_t N = 0;
-  int storage = 0;
-  bool shifted = false;
-  double tau = 0.0, omega = 0.0;
-  double g[3] = {0, 0, 0}, uw[3] = {0, 0, 0};
-  void* pop = nullptr;
-  size_t pop_bytes = 0;
-  unsigned char* aux = nullptr;
-  size_t aux_bytes = 0;
-  AuxLayout lay{};
-  hipStream_t stream = nullptr;
-  int device = 0;
-  bool has_geometry = false, initialized = false, all_fluid = false, has_moving_cells = false;
-  unsigned periodic = 0;
-  int phase = 0;
-  long long steps = 0;
-  long long nfluid = 0;
-  int bx = 256, nxb = 1;
-  // Replay of a captured run of graph_steps steps (0 = direct launches).  The
-  // graph bakes in the kernel arguments, so any parameter change drops it.
-  int graph_steps = 0;
-  hipGraphExec_t graph = nullptr;
-  std::string err;
-};
-
-namespace {
+namespace lbm_detail {
 
 thread_local std::string g_create_error;
 
@@ -646,12 +445,20 @@ lbm_status fail(lbm_lattice* h, lbm_status st, const std::string& msg) {
   return st;
 }
 
-#define HIP_TRY(h, call)                                                               \
-  do {                                                                                 \
-    hipError_t e_ = (call);                                                            \
-    if (e_ != hipSuccess)                                                              \
-      return fail((h), LBM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-  } while (0)
+void drop_graph(lbm_lattice* h) {
+  if (h->graph) {
+    (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+  }
+}
+
+}  // namespace lbm_detail
+
+using lbm_detail::drop_graph;
+using lbm_detail::fail;
+using lbm_detail::g_create_error;
+
+namespace {
 
 bool tau_ok(double tau) { return (std::isinf(tau) && tau > 0) || (std::isfinite(tau) && tau > 0.5); }
 
@@ -729,7 +536,7 @@ lbm_status check_dims(lbm_descriptor d, int nx, int ny, int nz, std::string* why
     *why = "D2Q9 needs nz == 1";
     return LBM_ERR_ARG;
   }
-  const double cells = (double)nx * ny * nz;
+  const double cells = (double)pop_stride((size_t)nx * ny * nz);
   if (cells * qof(d) >= 4294967296.0) {
     *why = "q*N must stay below 2^32 (32-bit population offsets)";
     return LBM_ERR_UNSUPPORTED;
@@ -777,6 +584,7 @@ struct Ops {
     const uint32_t* mov = (const uint32_t*)(h->aux + h->lay.mov);
     const dim3 grid((unsigned)(h->nxb * h->ny * h->nz)), block((unsigned)h->bx);
     const uint32_t N = (uint32_t)h->N;
+    const uint32_t PS = (uint32_t)h->ps;
     constexpr int C = Pack8<S>::C;
     const int tpr = h->nx / C;
     if (h->all_fluid && h->nx % C == 0 && tpr <= 256) {
@@ -784,14 +592,14 @@ struct Ops {
         const unsigned threads = 128;
         const unsigned nb = (unsigned)((h->N / C + threads - 1) / threads);
         hipLaunchKernelGGL((step_p0_flat_kernel<Q, S, SHIFT>), dim3(nb), dim3(threads), 0,
-                           h->stream, pop, N, p);
+                           h->stream, pop, N, PS, p);
       } else {
         const int rpb = tpr >= 256 ? 1 : 256 / tpr;
         const int rows = h->ny * h->nz;
         const unsigned nb = (unsigned)((rows + rpb - 1) / rpb);
         const size_t lds = (size_t)rpb * Shifted<Q>::count() * h->nx * sizeof(S);
         hipLaunchKernelGGL((step_p1_rows_kernel<Q, S, SHIFT>), dim3(nb), dim3(rpb * tpr), lds,
-                           h->stream, pop, h->nx, h->ny, h->nz, N, tpr, rpb, p);
+                           h->stream, pop, h->nx, h->ny, h->nz, PS, tpr, rpb, p);
       }
     } else if (!h->all_fluid && h->N % C == 0 && h->N >= 65536 && phase == 0) {
       // (small lattices are latency-bound: the per-cell kernel below, with
@@ -799,21 +607,21 @@ struct Ops {
       const unsigned threads = 128;
       const unsigned nb = (unsigned)((h->N / C + threads - 1) / threads);
       hipLaunchKernelGGL((step_p0_masked_kernel<Q, S, SHIFT>), dim3(nb), dim3(threads), 0,
-                         h->stream, pop, link, mov, N, p);
+                         h->stream, pop, link, mov, N, PS, p);
     } else if (h->all_fluid) {
       if (phase == 0)
         hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 0, false>), grid, block, 0, h->stream, pop,
-                           link, mov, h->nx, h->ny, h->nz, N, h->nxb, p);
+                           link, mov, h->nx, h->ny, h->nz, PS, h->nxb, p);
       else
         hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 1, false>), grid, block, 0, h->stream, pop,
-                           link, mov, h->nx, h->ny, h->nz, N, h->nxb, p);
+                           link, mov, h->nx, h->ny, h->nz, PS, h->nxb, p);
     } else {
       if (phase == 0)
         hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 0, true>), grid, block, 0, h->stream, pop,
-                           link, mov, h->nx, h->ny, h->nz, N, h->nxb, p);
+                           link, mov, h->nx, h->ny, h->nz, PS, h->nxb, p);
       else
         hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 1, true>), grid, block, 0, h->stream, pop,
-                           link, mov, h->nx, h->ny, h->nz, N, h->nxb, p);
+                           link, mov, h->nx, h->ny, h->nz, PS, h->nxb, p);
     }
   }
 
@@ -825,29 +633,30 @@ struct Ops {
   static void get_pop(lbm_lattice* h, double* out) {
     hipLaunchKernelGGL((get_pop_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
                        (const S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), out, h->nx,
-                       h->ny, h->nz, (uint32_t)h->N, h->phase);
+                       h->ny, h->nz, (uint32_t)h->N, (uint32_t)h->ps, h->phase);
   }
   static void set_pop(lbm_lattice* h, const double* in) {
     hipLaunchKernelGGL((set_pop_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
-                       (S*)h->pop, in, (uint32_t)h->N);
+                       (S*)h->pop, in, (uint32_t)h->N, (uint32_t)h->ps);
   }
   static void init_eq(lbm_lattice* h, const double* rho, const double* u) {
     hipLaunchKernelGGL((init_eq_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
                        (S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), rho, u,
-                       (uint32_t)h->N);
+                       (uint32_t)h->N, (uint32_t)h->ps);
   }
   static void moments(lbm_lattice* h, double* rho, double* u) {
     hipLaunchKernelGGL((moments_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
                        (const S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), rho, u, h->nx,
-                       h->ny, h->nz, (uint32_t)h->N, h->phase, h->g[0], h->g[1], h->g[2]);
+                       h->ny, h->nz, (uint32_t)h->N, (uint32_t)h->ps, h->phase, h->g[0], h->g[1],
+                       h->g[2]);
   }
   static void totals(lbm_lattice* h) {
     double* partials = (double*)(h->aux + h->lay.partials);
     double* result = (double*)(h->aux + h->lay.result);
     hipLaunchKernelGGL((totals_partial_kernel<Q, S, SHIFT>), dim3(RED_BLOCKS), dim3(RED_THREADS),
                        0, h->stream, (const S*)h->pop, (const uint32_t*)(h->aux + h->lay.link),
-                       partials, h->nx, h->ny, h->nz, (uint32_t)h->N, h->phase, h->g[0],
-                       h->g[1], h->g[2]);
+                       partials, h->nx, h->ny, h->nz, (uint32_t)h->N, (uint32_t)h->ps, h->phase,
+                       h->g[0], h->g[1], h->g[2]);
     hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(RED_THREADS), 0, h->stream, partials,
                        result, RED_BLOCKS);
   }
@@ -892,13 +701,6 @@ lbm_status launch_check(lbm_lattice* h) {
   return LBM_OK;
 }
 
-void drop_graph(lbm_lattice* h) {
-  if (h->graph) {
-    (void)hipGraphExecDestroy(h->graph);
-    h->graph = nullptr;
-  }
-}
-
 lbm_status enter(lbm_lattice* h) {
   if (!h) return LBM_ERR_ARG;
   h->err.clear();
@@ -920,7 +722,7 @@ lbm_status lbm_required_bytes(lbm_descriptor d, int nx, int ny, int nz, lbm_stor
   if (st) return fail(nullptr, st, why);
   if (storage_bytes(s) == 0) return fail(nullptr, LBM_ERR_ARG, "unknown storage type");
   const size_t N = (size_t)nx * ny * nz;
-  if (pop_bytes) *pop_bytes = align256((size_t)qof(d) * N * storage_bytes(s));
+  if (pop_bytes) *pop_bytes = align256((size_t)qof(d) * pop_stride(N) * storage_bytes(s));
   if (aux_bytes) *aux_bytes = aux_layout(N).total;
   return LBM_OK;
 }
@@ -966,6 +768,7 @@ lbm_status lbm_lattice_create(lbm_lattice** out, lbm_descriptor d, int nx, int n
   h->ny = ny;
   h->nz = nz;
   h->N = (size_t)nx * ny * nz;
+  h->ps = pop_stride(h->N);
   h->storage = s;
   h->shifted = (flags & LBM_FLAG_SHIFTED) != 0;
   h->tau = tau;
@@ -990,6 +793,7 @@ lbm_status lbm_lattice_create(lbm_lattice** out, lbm_descriptor d, int nx, int n
 lbm_status lbm_set_geometry(lbm_lattice* h, const uint8_t* material, unsigned periodic_mask) {
   lbm_status st = enter(h);
   if (st) return st;
+  if (h->batch) return fail(h, LBM_ERR_STATE, "lattice belongs to a batch: use the lbm_batch_* calls");
   if (!material) return fail(h, LBM_ERR_ARG, "material is NULL");
   if (periodic_mask > 7u) return fail(h, LBM_ERR_ARG, "periodic_mask uses bits 0..2 only");
   std::vector<uint32_t> link, mov;
@@ -1020,6 +824,7 @@ lbm_status lbm_set_geometry(lbm_lattice* h, const uint8_t* material, unsigned pe
 
 lbm_status lbm_set_wall_velocity(lbm_lattice* h, const double u_w[3]) {
   if (!h) return LBM_ERR_ARG;
+  if (h->batch) return fail(h, LBM_ERR_STATE, "lattice belongs to a batch: use the lbm_batch_* calls");
   if (!u_w) return fail(h, LBM_ERR_ARG, "u_w is NULL");
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(u_w[a])) return fail(h, LBM_ERR_ARG, "u_w must be finite");
@@ -1031,6 +836,7 @@ lbm_status lbm_set_wall_velocity(lbm_lattice* h, const double u_w[3]) {
 
 lbm_status lbm_set_body_force(lbm_lattice* h, const double g[3]) {
   if (!h) return LBM_ERR_ARG;
+  if (h->batch) return fail(h, LBM_ERR_STATE, "lattice belongs to a batch: use the lbm_batch_* calls");
   if (!g) return fail(h, LBM_ERR_ARG, "g is NULL");
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(g[a])) return fail(h, LBM_ERR_ARG, "g must be finite");
@@ -1042,6 +848,7 @@ lbm_status lbm_set_body_force(lbm_lattice* h, const double g[3]) {
 
 lbm_status lbm_set_tau(lbm_lattice* h, double tau) {
   if (!h) return LBM_ERR_ARG;
+  if (h->batch) return fail(h, LBM_ERR_STATE, "lattice belongs to a batch: use the lbm_batch_* calls");
   if (!tau_ok(tau)) return fail(h, LBM_ERR_ARG, "tau must be > 0.5 (or +inf for pure streaming)");
   h->tau = tau;
   h->omega = std::isinf(tau) ? 0.0 : 1.0 / tau;
@@ -1088,6 +895,7 @@ lbm_status lbm_get_populations(lbm_lattice* h, double* f_dev) {
 lbm_status lbm_step(lbm_lattice* h, int n) {
   lbm_status st = enter(h);
   if (st) return st;
+  if (h->batch) return fail(h, LBM_ERR_STATE, "lattice belongs to a batch: use the lbm_batch_* calls");
   if (n < 0) return fail(h, LBM_ERR_ARG, "n must be >= 0");
   if (!h->initialized) return fail(h, LBM_ERR_STATE, "initialise the populations first");
   const OpTable t = ops(h);
@@ -1132,6 +940,7 @@ lbm_status lbm_step(lbm_lattice* h, int n) {
 lbm_status lbm_set_graph_steps(lbm_lattice* h, int steps) {
   lbm_status st = enter(h);
   if (st) return st;
+  if (h->batch) return fail(h, LBM_ERR_STATE, "lattice belongs to a batch: use the lbm_batch_* calls");
   if (steps < 0 || (steps & 1)) return fail(h, LBM_ERR_ARG, "graph length must be even and >= 0");
   if (steps > 0 && h->stream == nullptr)
     return fail(h, LBM_ERR_ARG, "graph replay needs a created (non-null) stream");
@@ -1182,6 +991,7 @@ lbm_status lbm_get_info(const lbm_lattice* h, long long* steps, long long* fluid
 
 lbm_status lbm_lattice_destroy(lbm_lattice* h) {
   if (!h) return LBM_ERR_ARG;
+  if (h->batch) return fail(h, LBM_ERR_STATE, "lattice belongs to a batch: use the lbm_batch_* calls");
   hipError_t e = hipSetDevice(h->device);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   drop_graph(h);

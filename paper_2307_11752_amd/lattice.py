@@ -47,7 +47,14 @@ def _vec3(v):
     return out
 
 
-class Lattice:
+class _Handle:
+    """Calls shared by owned lattices and batch members (``self.h`` is the C handle)."""
+
+    def _chk(self, st):
+        return check(st, self.h)
+
+
+class Lattice(_Handle):
     """One lattice (one block) on the current GPU.
 
     shape = (nx, ny, nz); populations live in a caller-owned uint8 tensor
@@ -93,9 +100,6 @@ class Lattice:
             self.close()
         except Exception:
             pass
-
-    def _chk(self, st):
-        return check(st, self.h)
 
     # -- set-up -------------------------------------------------------------
     def set_geometry(self, material, periodic):

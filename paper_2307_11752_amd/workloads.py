@@ -69,6 +69,21 @@ def tgv3d(n=256, u0=0.05, tau=0.8, steps=1000, storage="f32", with_field=True):
                     steps, storage)
 
 
+def tgv_ensemble(count=256, seed=1107, lmin=16, lmax=96, u0_range=(0.01, 0.08),
+                 tau_range=(0.55, 1.0)):
+    """Ensemble of periodic D3Q19 Taylor-Green lattices: every edge length
+    log-uniform in [lmin, lmax] (independently per axis, so boxes are not
+    cubic), u0 uniform in u0_range, tau uniform in tau_range.  Returns
+    (shapes [(nx, ny, nz)], u0 [count], tau [count]); the initial field of
+    member l is tgv3d_velocity(*shapes[l], u0[l])."""
+    rng = np.random.default_rng(seed)
+    lo, hi = math.log(lmin), math.log(lmax)
+    shapes = [tuple(int(round(math.exp(v))) for v in rng.uniform(lo, hi, 3)) for _ in range(count)]
+    u0 = rng.uniform(*u0_range, count)
+    tau = rng.uniform(*tau_range, count)
+    return shapes, u0, tau
+
+
 def channel_spheres(nx=512, ny=128, nz=128, seed=2307, solid_fraction=0.20, rmin=4.0,
                     rmax=10.0, g=1e-6, tau=0.7, steps=5000, storage="f32"):
     """Body-force-driven channel: periodic along x, resting walls on the outer y

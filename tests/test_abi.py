@@ -43,8 +43,9 @@ def test_required_bytes(lib):
     assert a.value >= 8 * 256**3
     assert lib.lbm_required_bytes(0, 64, 64, 1, _lib.STORE_F64, ctypes.byref(p), ctypes.byref(a)) == 0
     assert p.value == 9 * 64 * 64 * 8
+    # population arrays are PS = N rounded up to 64 elements apart
     assert lib.lbm_required_bytes(1, 10, 10, 10, _lib.STORE_F16, ctypes.byref(p), None) == 0
-    assert p.value == ((19 * 1000 * 2 + 255) // 256) * 256
+    assert p.value == ((19 * 1024 * 2 + 255) // 256) * 256
     assert lib.lbm_required_bytes(0, 8, 8, 2, 0, ctypes.byref(p), None) == _lib.ERR_ARG
     assert lib.lbm_required_bytes(1, 0, 8, 8, 0, ctypes.byref(p), None) == _lib.ERR_ARG
     assert lib.lbm_required_bytes(1, 8, 8, 8, 9, ctypes.byref(p), None) == _lib.ERR_ARG

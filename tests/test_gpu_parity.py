@@ -41,6 +41,7 @@ CASES_3D = [
     ((5, 4, 6), 0b111),
     ((70, 9, 7), 0b011),   # more than one x-block of 64 threads, ragged tail
     ((300, 4, 3), 0b111),  # two 256-wide x-blocks, ragged tail
+    ((64, 34, 32), 0b001),  # >= 65536 cells: masked lattices take the flat phase-0 kernel
 ]
 CASES_2D = [
     ((9, 7, 1), 0b00),
@@ -191,7 +192,9 @@ def test_fp64_full_steps(orc, lbm, shifted, d, case):
     m_g, j_g, s_g = gpu.totals()
     m_o, j_o, s_o = ref.totals()
     assert abs(m_g - m_o) <= 1e-12 * m_o
-    np.testing.assert_allclose(j_g, j_o, rtol=0, atol=1e-12)
+    # the two sides sum N per-cell momenta (each below 1) in different orders:
+    # rounding differs by at most about N * eps
+    np.testing.assert_allclose(j_g, j_o, rtol=0, atol=1e-15 * mat.size)
     np.testing.assert_allclose(s_g, s_o, rtol=1e-11, atol=1e-15)
 
 
@@ -220,7 +223,7 @@ def test_fp64_full_steps_fluid_box(orc, lbm, shifted, d, shape):
 @pytest.mark.parametrize("storage,shifted", [("f64", True), ("f32", False), ("f32", True),
                                              ("f16", True), ("bf16", True)])
 @pytest.mark.parametrize("d,case", [(1, CASES_3D[0]), (1, CASES_3D[3]), (1, CASES_3D[4]),
-                                    (0, CASES_2D[0]), (0, CASES_2D[3]),
+                                    (1, CASES_3D[6]), (0, CASES_2D[0]), (0, CASES_2D[3]),
                                     (1, ((64, 4, 3), "fluid")), (1, ((12, 5, 4), "fluid")),
                                     (0, ((128, 6, 1), "fluid"))])
 @pytest.mark.parametrize("parity", [0, 1])
