@@ -73,12 +73,18 @@ def _load():
         "orc_moments": [I, I, I, I, P, P, P, P, P],
         "orc_totals": [I, I, I, I, P, P, P, P, P, P],
         "orc_num_threads": [],
+        "orc_porous_collide": [I, D, P, D, P, P, P],
+        "orc_porous_step": [I, I, I, I, P, U, D, P, P, P, P, I],
+        "orc_porous_objective": [I, I, I, I, P, P, P, I],
+        "orc_porous_gradient": [I, I, I, I, P, U, D, P, P, I, P, I, P, P, I],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = None if name in ("orc_equilibrium", "orc_guo_source",
-                                      "orc_cell_moments", "orc_collide") else I
+                                      "orc_cell_moments", "orc_collide",
+                                      "orc_porous_collide") else I
+    lib.orc_porous_objective.restype = D
     _lib = lib
     return lib
 
@@ -235,3 +241,72 @@ def check_geometry(d, mat, periodic) -> int:
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+# ---------------------------------------------------------------------------
+# Porous BGK (Simulation Models, "Porous Media Model") and its discrete adjoint
+# ---------------------------------------------------------------------------
+def porous_collide(d, omega, f, por, g=None):
+    lib = _load()
+    f = _f64(f, q_of(d)).copy()
+    rho = np.zeros(1)
+    u = np.zeros(3)
+    lib.orc_porous_collide(d, float(omega), _p(_vec3(g)), float(por), _p(f), _p(rho), _p(u))
+    return f, rho[0], u
+
+
+class PorousProblem:
+    """Channel with a per-cell porosity field d (shape (nz, ny, nx)); forward
+    runs of the porous step, the outlet-plane objective and its FP64 adjoint
+    gradient with respect to d."""
+
+    def __init__(self, d, mat, periodic, tau, g, plane_x=None, nthreads=0):
+        self.d = d
+        self.q = q_of(d)
+        mat = np.ascontiguousarray(mat, dtype=np.uint8)
+        if mat.ndim == 2:
+            mat = mat[None]
+        self.mat = mat
+        self.nz, self.ny, self.nx = mat.shape
+        self.N = mat.size
+        self.periodic = int(periodic)
+        self.omega = 1.0 / float(tau)
+        self.g = _vec3(g)
+        self.plane_x = self.nx - 1 if plane_x is None else int(plane_x)
+        self.nthreads = int(nthreads)
+
+    def initial_state(self):
+        lat = Lattice(self.d, self.mat, self.periodic, 1.0 / self.omega, g=self.g)
+        lat.init_equilibrium()
+        return lat.f.copy()
+
+    def forward(self, por, nsteps, f0=None):
+        """(J, f^T) after nsteps porous steps from f0 (default: rest, rho = 1)."""
+        lib = _load()
+        por = _f64(por, self.N)
+        a = self.initial_state() if f0 is None else np.array(f0, dtype=np.float64)
+        b = np.empty_like(a)
+        for _ in range(nsteps):
+            st = lib.orc_porous_step(self.d, self.nx, self.ny, self.nz, _p(self.mat),
+                                     self.periodic, self.omega, _p(self.g), _p(por), _p(a),
+                                     _p(b), self.nthreads)
+            if st:
+                raise RuntimeError(f"porous step failed ({st})")
+            a, b = b, a
+        J = lib.orc_porous_objective(self.d, self.nx, self.ny, self.nz, _p(self.mat),
+                                     _p(self.g), _p(a), self.plane_x)
+        return J, a
+
+    def gradient(self, por, nsteps, f0=None):
+        """(J, dJ/dd) by the discrete adjoint, all in FP64."""
+        lib = _load()
+        por = _f64(por, self.N)
+        f0 = self.initial_state() if f0 is None else _f64(f0)
+        J = np.zeros(1)
+        grad = np.zeros(self.N)
+        st = lib.orc_porous_gradient(self.d, self.nx, self.ny, self.nz, _p(self.mat),
+                                     self.periodic, self.omega, _p(self.g), _p(por), int(nsteps),
+                                     _p(f0), self.plane_x, _p(J), _p(grad), self.nthreads)
+        if st:
+            raise RuntimeError(f"oracle adjoint failed ({st})")
+        return J[0], grad.reshape(self.mat.shape)

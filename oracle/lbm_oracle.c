@@ -431,3 +431,222 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* ===========================================================================
+ * Porous BGK and its discrete adjoint.
+ *
+ * Porous media model (Simulation Models, "Porous Media Model"): each cell
+ * carries a porosity d in [0, 1] (0 solid, 1 fluid), a factor that scales the
+ * velocity of the Maxwellian (the guide's latticePorosity comment).  Reading
+ * R15: the equilibrium and the Guo term both use v = d u with the
+ * force-shifted u = j/rho + g/2; d = 1 is exactly the plain collision above.
+ * Only resting walls (material 2) are allowed with porosity.
+ * ========================================================================= */
+void orc_porous_collide(int d, double omega, const double *g, double por, double *f,
+                        double *rho_out, double *u_out) {
+  desc_t D;
+  if (get_desc(d, &D)) return;
+  double rho, u[3], v[3] = {0.0, 0.0, 0.0}, feq[19], S[19];
+  orc_cell_moments(d, f, g, &rho, u);
+  for (int a = 0; a < D.dim; ++a) v[a] = por * u[a];
+  orc_equilibrium(d, rho, v, feq);
+  orc_guo_source(d, omega, rho, v, g, S);
+  for (int i = 0; i < D.q; ++i) {
+    f[i] = (1.0 - omega) * f[i];
+    f[i] = f[i] + omega * feq[i];
+    f[i] = f[i] + S[i];
+  }
+  if (rho_out) *rho_out = rho;
+  if (u_out) for (int a = 0; a < 3; ++a) u_out[a] = u[a];
+}
+
+int orc_porous_step(int d, int nx, int ny, int nz, const uint8_t *mat, unsigned periodic,
+                    double omega, const double *g, const double *por, const double *A,
+                    double *B, int nthreads) {
+  desc_t D;
+  if (get_desc(d, &D) || !mat || !A || !B || !g || !por) return ORC_ERR_ARG;
+  const long N = (long)nx * ny * nz;
+  const int q = D.q;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+  for (long idx = 0; idx < N; ++idx) {
+    if (mat[idx] == MAT_MOVING) return ORC_ERR_UNSUPPORTED;
+    if (mat[idx] != MAT_FLUID)
+      for (int i = 0; i < q; ++i) B[i * N + idx] = A[i * N + idx];
+  }
+#pragma omp parallel for schedule(static)
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const long idx = x + (long)nx * (y + (long)ny * z);
+        if (mat[idx] != MAT_FLUID) continue;
+        double f[19];
+        for (int i = 0; i < q; ++i) f[i] = A[i * N + idx];
+        orc_porous_collide(d, omega, g, por[idx], f, NULL, NULL);
+        for (int i = 0; i < q; ++i) {
+          int ok = 1;
+          const int xn = wrap_coord(x + D.c[i][0], nx, periodic & 1u, &ok);
+          const int yn = wrap_coord(y + D.c[i][1], ny, periodic & 2u, &ok);
+          const int zn = wrap_coord(z + D.c[i][2], nz, periodic & 4u, &ok);
+          const long nb = xn + (long)nx * (yn + (long)ny * zn);
+          if (ok && mat[nb] == MAT_FLUID)
+            B[i * N + nb] = f[i];
+          else
+            B[D.opp[i] * N + idx] = f[i];
+        }
+      }
+  return ORC_OK;
+}
+
+/* Objective: mean x-velocity (force-shifted, as reported by the moments) over
+ * the fluid cells of the plane x = plane_x. */
+double orc_porous_objective(int d, int nx, int ny, int nz, const uint8_t *mat,
+                            const double *g, const double *f, int plane_x) {
+  desc_t D;
+  if (get_desc(d, &D)) return NAN;
+  const long N = (long)nx * ny * nz;
+  double sum = 0.0;
+  long n = 0;
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y) {
+      const long idx = plane_x + (long)nx * (y + (long)ny * z);
+      if (mat[idx] != MAT_FLUID) continue;
+      double fc[19], rho, u[3];
+      for (int i = 0; i < D.q; ++i) fc[i] = f[i * N + idx];
+      orc_cell_moments(d, fc, g, &rho, u);
+      sum += u[0];
+      ++n;
+    }
+  return n ? sum / n : 0.0;
+}
+
+/* Discrete adjoint of the porous step, reverse over all time steps.
+ * Forward: f^{t+1} = Stream(Collide(f^t; d)), J = objective(f^T).
+ * lambda^T = dJ/df^T; for t = T-1 .. 0:
+ *   mu = Stream^T lambda^{t+1}   (pull: mu_i(x) = lambda_i(x + c_i), or
+ *                                  lambda_opp(i)(x) across a wall)
+ *   lambda^t = (dCollide/df)^T mu,  dJ/dd += (dCollide/dd)^T mu,
+ * both at the state f^t.  With v = d u, u = j/rho + g/2:
+ *   dfeq_i/dv_a = w_i rho (3 c_ia + 9 (c_i.v) c_ia - 3 v_a)
+ *   dS_i/dv_a   = (1 - omega/2) w_i (-3 F_a + 9 c_ia (c_i.F)),  F = rho g
+ *   dfeq_i/drho|v = feq_i / rho,  dS_i/drho|v = S_i / rho
+ *   dv_a/drho = -d j_a / rho^2,  dv_a/dj_b = d delta_ab / rho,  dv_a/dd = u_a
+ * All states f^0 .. f^T are kept (no checkpointing).  J and grad[N] are
+ * outputs; grad is zero on non-fluid cells. */
+int orc_porous_gradient(int d, int nx, int ny, int nz, const uint8_t *mat, unsigned periodic,
+                        double omega, const double *g, const double *por, int nsteps,
+                        const double *f0, int plane_x, double *J, double *grad, int nthreads) {
+  desc_t D;
+  if (get_desc(d, &D) || nsteps < 0 || !f0 || !grad || !J || plane_x < 0 || plane_x >= nx)
+    return ORC_ERR_ARG;
+  const long N = (long)nx * ny * nz;
+  const int q = D.q;
+  const size_t state = (size_t)q * (size_t)N;
+  double *hist = (double *)malloc(sizeof(double) * state * (size_t)(nsteps + 1));
+  double *lam = (double *)calloc(state, sizeof(double));
+  double *lam_prev = (double *)calloc(state, sizeof(double));
+  if (!hist || !lam || !lam_prev) {
+    free(hist); free(lam); free(lam_prev);
+    return ORC_ERR_ARG;
+  }
+  memcpy(hist, f0, sizeof(double) * state);
+  for (int t = 0; t < nsteps; ++t) {
+    int st = orc_porous_step(d, nx, ny, nz, mat, periodic, omega, g, por, hist + state * t,
+                             hist + state * (t + 1), nthreads);
+    if (st) {
+      free(hist); free(lam); free(lam_prev);
+      return st;
+    }
+  }
+  const double *fT = hist + state * (size_t)nsteps;
+  *J = orc_porous_objective(d, nx, ny, nz, mat, g, fT, plane_x);
+
+  /* lambda^T: derivative of the plane mean of u_x = j_x/rho + g_x/2 */
+  long nplane = 0;
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      if (mat[plane_x + (long)nx * (y + (long)ny * z)] == MAT_FLUID) ++nplane;
+  for (int z = 0; z < nz && nplane; ++z)
+    for (int y = 0; y < ny; ++y) {
+      const long idx = plane_x + (long)nx * (y + (long)ny * z);
+      if (mat[idx] != MAT_FLUID) continue;
+      double rho = 0.0, jx = 0.0;
+      for (int i = 0; i < q; ++i) {
+        rho += fT[i * N + idx];
+        jx += D.c[i][0] * fT[i * N + idx];
+      }
+      for (int i = 0; i < q; ++i)
+        lam[i * N + idx] = (D.c[i][0] / rho - jx / (rho * rho)) / (double)nplane;
+    }
+  for (long idx = 0; idx < N; ++idx) grad[idx] = 0.0;
+  const double k = 1.0 - omega / 2.0;
+
+  for (int t = nsteps - 1; t >= 0; --t) {
+    const double *ft = hist + state * (size_t)t;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const long idx = x + (long)nx * (y + (long)ny * z);
+          if (mat[idx] != MAT_FLUID) {
+            for (int i = 0; i < q; ++i) lam_prev[i * N + idx] = 0.0;
+            continue;
+          }
+          double mu[19], fc[19], feq[19], S[19];
+          for (int i = 0; i < q; ++i) {
+            int ok = 1;
+            const int xn = wrap_coord(x + D.c[i][0], nx, periodic & 1u, &ok);
+            const int yn = wrap_coord(y + D.c[i][1], ny, periodic & 2u, &ok);
+            const int zn = wrap_coord(z + D.c[i][2], nz, periodic & 4u, &ok);
+            const long nb = xn + (long)nx * (yn + (long)ny * zn);
+            if (ok && mat[nb] == MAT_FLUID)
+              mu[i] = lam[i * N + nb];
+            else
+              mu[i] = lam[D.opp[i] * N + idx];
+            fc[i] = ft[i * N + idx];
+          }
+          double rho, u[3], v[3] = {0.0, 0.0, 0.0}, j[3] = {0.0, 0.0, 0.0};
+          orc_cell_moments(d, fc, g, &rho, u);
+          for (int i = 0; i < q; ++i)
+            for (int a = 0; a < D.dim; ++a) j[a] += D.c[i][a] * fc[i];
+          const double dp = por[idx];
+          for (int a = 0; a < D.dim; ++a) v[a] = dp * u[a];
+          orc_equilibrium(d, rho, v, feq);
+          orc_guo_source(d, omega, rho, v, g, S);
+          double F[3] = {0.0, 0.0, 0.0};
+          for (int a = 0; a < D.dim; ++a) F[a] = rho * g[a];
+          double G[3] = {0.0, 0.0, 0.0}, E = 0.0;
+          for (int i = 0; i < q; ++i) {
+            double cv = 0.0, cF = 0.0;
+            for (int a = 0; a < D.dim; ++a) {
+              cv += D.c[i][a] * v[a];
+              cF += D.c[i][a] * F[a];
+            }
+            for (int a = 0; a < D.dim; ++a) {
+              const double dfeq = D.w[i] * rho * (3.0 * D.c[i][a] + 9.0 * cv * D.c[i][a] - 3.0 * v[a]);
+              const double dS = k * D.w[i] * (-3.0 * F[a] + 9.0 * D.c[i][a] * cF);
+              G[a] += mu[i] * (omega * dfeq + dS);
+            }
+            E += mu[i] * (omega * feq[i] + S[i]) / rho;
+          }
+          double gsum = 0.0, Gj = 0.0;
+          for (int a = 0; a < D.dim; ++a) {
+            gsum += G[a] * u[a];
+            Gj += G[a] * j[a];
+          }
+          grad[idx] += gsum;
+          const double Arho = E - dp * Gj / (rho * rho);
+          for (int i = 0; i < q; ++i) {
+            double s = (1.0 - omega) * mu[i] + Arho;
+            for (int a = 0; a < D.dim; ++a) s += dp * G[a] / rho * D.c[i][a];
+            lam_prev[i * N + idx] = s;
+          }
+        }
+    double *tmp = lam; lam = lam_prev; lam_prev = tmp;
+  }
+  free(hist); free(lam); free(lam_prev);
+  return ORC_OK;
+}

@@ -460,3 +460,71 @@ def test_statistics_definitions(orc):
     assert abs(s[1] - 0.5 * np.mean(np.sum(u**2, axis=0))) < 1e-14
     assert abs(s[2] - np.max(np.sqrt(np.sum(u**2, axis=0)))) < 1e-14
     np.testing.assert_allclose(j[:2], np.sum(rho * u, axis=(1, 2, 3)), atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Porous BGK (Simulation Models, "Porous Media Model") and its FP64 adjoint
+# ---------------------------------------------------------------------------
+def test_porous_step_with_unit_porosity_is_the_plain_step(orc):
+    """d = 1 means pure fluid: the porous step must equal the plain BGK + Guo
+    step bit for bit (walls, periodic x, body force)."""
+    sh = (4, 5, 6)
+    mat = np.ones(sh, np.uint8)
+    mat[:, 0, :] = 2
+    mat[:, -1, :] = 2
+    g = [1e-4, 2e-5, -3e-5]
+    rng = np.random.default_rng(0)
+    lat = orc.Lattice(1, mat, 0b101, 0.7, g=g)
+    lat.init_equilibrium(None, rng.uniform(-0.05, 0.05, (3,) + sh))
+    f0 = lat.f.copy()
+    prob = orc.PorousProblem(1, mat, 0b101, 0.7, g)
+    _, fT = prob.forward(np.ones(sh), 6, f0=f0)
+    lat.step(6)
+    assert np.array_equal(fT[:, mat == 1], lat.f[:, mat == 1])
+
+
+@pytest.mark.parametrize("K", [0.05, 0.2, 2.0])
+def test_porous_darcy_law_with_guide_permeability(orc, K):
+    """The guide's discrete porosity of a permeability K is
+    d = 1 - h^(dim-1) nu tau / K (lattice units, h = 1).  In a periodic box with
+    uniform d and body acceleration g the porous step reaches the uniform
+    steady velocity u = g / (omega (1 - d)) = K g / nu: Darcy's law."""
+    tau = 0.7
+    nu = (tau - 0.5) / 3.0
+    d = 1.0 - nu * tau / K
+    assert 0.0 <= d < 1.0
+    g = 1e-6
+    mat = np.ones((2, 3, 4), np.uint8)
+    prob = orc.PorousProblem(1, mat, 7, tau, [g, 0, 0])
+    J, fT = prob.forward(np.full(mat.shape, d), 4000)
+    assert abs(J / (K * g / nu) - 1.0) < 1e-9
+
+
+def test_porous_adjoint_matches_central_differences(orc):
+    """The FP64 discrete adjoint gradient of the outlet-plane mean velocity
+    with respect to the porosity of single cells equals the central difference
+    quotient of the FP64 forward model (the guide's difference-quotient
+    derivative option) to the difference quotient's own accuracy."""
+    sh = (5, 6, 8)
+    mat = np.ones(sh, np.uint8)
+    mat[:, 0, :] = 2
+    mat[:, -1, :] = 2
+    mat[0, :, :] = 2
+    mat[-1, :, :] = 2
+    rng = np.random.default_rng(1)
+    por = rng.uniform(0.3, 1.0, sh)
+    prob = orc.PorousProblem(1, mat, 0b001, 0.7, [1e-4, 0, 0])
+    J, grad = prob.gradient(por, 40)
+    J2, _ = prob.forward(por, 40)
+    assert J == J2
+    assert np.all(grad[mat != 1] == 0.0)
+    fluid = np.argwhere(mat == 1)
+    for c in fluid[rng.choice(len(fluid), 8, replace=False)]:
+        c = tuple(c)
+        h = 1e-4
+        pp = por.copy()
+        pp[c] += h
+        pm = por.copy()
+        pm[c] -= h
+        fd = (prob.forward(pp, 40)[0] - prob.forward(pm, 40)[0]) / (2 * h)
+        assert abs(grad[c] - fd) <= 1e-6 * abs(fd), (c, grad[c], fd)
