@@ -191,6 +191,31 @@ def bench_ensemble(args):
     alg_bytes = cells * 2 * 19 * sb
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
     mlups = cells * args.steps / wall / 1e6
+
+    # the same lattices stepped one by one (each its own handle, launches and
+    # 100-step graph) -- what the batch replaces
+    batch.close()
+    del batch
+    torch.cuda.empty_cache()
+    singles = []
+    for s_, t_, u_ in zip(shapes, taus, fields):
+        lt = P.Lattice(1, s_, t_, storage=storage, shifted=shifted, stream=stream)
+        lt.set_geometry(np.ones(tuple(reversed(s_)), np.uint8), 7)
+        lt.init_equilibrium(None, u_)
+        if args.graph_steps:
+            lt.set_graph_steps(args.graph_steps)
+        singles.append(lt)
+    usteps = max(2, min(args.steps, 200) // 2 * 2)
+    for lt in singles:
+        lt.step(2)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for lt in singles:
+        lt.step(usteps)
+    torch.cuda.synchronize()
+    unbatched = cells * usteps / (time.perf_counter() - t1) / 1e6
+    for lt in singles:
+        lt.close()
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -218,6 +243,8 @@ def bench_ensemble(args):
                      "kernel": f"batch_step_kernel<Q=19,{storage}>"},
         "cpu_baseline": cpu,
         "oracle_parity": parity,
+        "unbatched_mlups": round(unbatched, 2),
+        "unbatched_note": f"each lattice as its own handle, {usteps} steps each in turn",
     }
     print(json.dumps(out), flush=True)
 

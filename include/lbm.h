@@ -233,6 +233,50 @@ lbm_status lbm_batch_destroy(lbm_batch* b);
 
 const char* lbm_batch_last_error(const lbm_batch* b);
 
+/* ---------------------------------------------------------------------------
+ * Porous channel and its discrete adjoint (D3Q19, FP32 storage and arithmetic).
+ *
+ * Model: the guide's porous media model (Simulation Models, "Porous Media
+ * Model"): a per-cell porosity d in [0, 1] (0 solid, 1 fluid) scales the
+ * velocity of the Maxwellian.  The fused collision uses v = d u, u = j/rho +
+ * g/2, in both the second-order equilibrium and the Guo term (d = 1 is the
+ * plain BGK + Guo collision); resting bounce-back walls (material 2) and
+ * periodic axes as for lbm_set_geometry; moving walls are refused.
+ * Objective J: the mean force-shifted x-velocity over the fluid cells of the
+ * plane x = plane_x after `steps` steps from rest (rho = 1, u = 0).
+ * Gradient dJ/dd by the discrete adjoint of the scheme (the guide's adjoint
+ * LBM option, Flow Control and Optimization, "Derivative Computation"),
+ * reverse in time with the forward states recomputed from checkpoints taken
+ * every `checkpoint_every` steps.  All device memory is one caller-owned
+ * work buffer of lbm_porous_required_bytes.
+ * ------------------------------------------------------------------------- */
+typedef struct lbm_porous lbm_porous; /* opaque handle */
+
+lbm_status lbm_porous_required_bytes(int nx, int ny, int nz, int steps, int checkpoint_every,
+                                     size_t* work_bytes);
+
+/* material: host, N bytes (copied); g: host body acceleration; plane_x: the
+ * objective plane (0 <= plane_x < nx). */
+lbm_status lbm_porous_create(lbm_porous** out, int nx, int ny, int nz, double tau,
+                             const uint8_t* material, unsigned periodic_mask, const double g[3],
+                             int steps, int checkpoint_every, int plane_x, void* dev_work,
+                             size_t work_bytes, void* hip_stream);
+
+/* Run the forward problem for porosity_dev (device float[N], copied) and
+ * return J (host).  Keeps the checkpoints for lbm_porous_backward.  sync. */
+lbm_status lbm_porous_forward(lbm_porous* h, const float* porosity_dev, double* J);
+
+/* dJ/dd for the porosity of the last forward run into grad_dev (device
+ * float[N]; zero on non-fluid cells).  sync. */
+lbm_status lbm_porous_backward(lbm_porous* h, float* grad_dev);
+
+/* Final populations of the last forward run, device double[19*N], natural
+ * layout (f_i of cell idx at i*N + idx).  sync. */
+lbm_status lbm_porous_get_final(lbm_porous* h, double* f_dev);
+
+lbm_status lbm_porous_destroy(lbm_porous* h);
+const char* lbm_porous_last_error(const lbm_porous* h);
+
 const char* lbm_status_string(lbm_status st);
 /* Message of the last failed call on h ("" if none); h may be NULL for
  * failures of lbm_lattice_create. */

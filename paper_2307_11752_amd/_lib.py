@@ -70,6 +70,13 @@ SIGNATURES = {
     "lbm_batch_get_info": ([_P, _PI, _PLL, _PI, _PI], _I),
     "lbm_batch_destroy": ([_P], _I),
     "lbm_batch_last_error": ([_P], ctypes.c_char_p),
+    "lbm_porous_required_bytes": ([_I, _I, _I, _I, _I, _PSZ], _I),
+    "lbm_porous_create": ([_PP, _I, _I, _I, _D, _P, _U, _P, _I, _I, _I, _P, _SZ, _P], _I),
+    "lbm_porous_forward": ([_P, _P, _PD], _I),
+    "lbm_porous_backward": ([_P, _P], _I),
+    "lbm_porous_get_final": ([_P, _P], _I),
+    "lbm_porous_destroy": ([_P], _I),
+    "lbm_porous_last_error": ([_P], ctypes.c_char_p),
 }
 
 _lib = None
@@ -103,6 +110,15 @@ def check(status, handle=None):
     if status != OK:
         lib = load()
         msg = lib.lbm_last_error(handle).decode() or lib.lbm_status_string(status).decode()
+        raise LBMError(status, msg)
+    return status
+
+
+def check_porous(status, handle):
+    if status != OK:
+        lib = load()
+        msg = (lib.lbm_porous_last_error(handle).decode() if handle else "") or \
+            lib.lbm_last_error(None).decode() or lib.lbm_status_string(status).decode()
         raise LBMError(status, msg)
     return status
 

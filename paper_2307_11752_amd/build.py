@@ -8,9 +8,9 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", "lbm.hip"), os.path.join(HERE, "csrc", "batch.hip")]
-DEPS = SRC + [os.path.join(HERE, "csrc", "lattice.hpp"), os.path.join(HERE, "csrc", "handle.hpp"),
-               os.path.join(ROOT, "include", "lbm.h")]
+SRC = [os.path.join(HERE, "csrc", n) for n in ("lbm.hip", "batch.hip", "adjoint.hip")]
+DEPS = SRC + [os.path.join(HERE, "csrc", n) for n in ("lattice.hpp", "handle.hpp", "fluid_path.hpp")] \
+    + [os.path.join(ROOT, "include", "lbm.h")]
 LIB = os.path.join(HERE, "liblbm_hip.so")
 ARCH = "gfx950"
 

@@ -1,0 +1,526 @@
+// adjoint.hip -- porous D3Q19 channel and its hand-written discrete adjoint:
+// the gradient of an outlet-plane objective with respect to a per-cell
+// porosity field, by reverse time stepping with checkpointed recomputation.
+//
+// Model (OpenLB User Guide 1.6, Simulation Models, "Porous Media Model"): the
+// porosity d in [0, 1] (0 solid, 1 fluid) scales the velocity of the
+// Maxwellian; here the equilibrium and the Guo term of the fused BGK
+// collision both use v = d u with the force-shifted u = j/rho + g/2, and
+// d = 1 is the plain collision.  Objective: the mean force-shifted x-velocity
+// over the fluid cells of one x-plane after `steps` steps from rest.
+// Gradients: the guide's adjoint-LBM option of "Derivative Computation"
+// (Flow Control and Optimization), derived for this discrete scheme:
+//   mu = Stream^T lambda^{t+1}; lambda^t = (dC/df)^T mu; dJ/dd += (dC/dd)^T mu
+// at the state f^t (C = collision).  With G_a = sum_i mu_i (omega dfeq_i/dv_a
+// + dS_i/dv_a) and E = sum_i mu_i (omega feq_i + S_i) / rho:
+//   lambda^t_j = (1 - omega) mu_j + E - d (G.j)/rho^2 + (d/rho) G.c_j
+//   dJ/dd     += G.u
+// Storage and arithmetic are FP32 (the objective is reduced in FP64); the
+// stored value is f_i - w_i, so that the small deviations from rest keep
+// their precision (the gradient with respect to f is unchanged by the shift).
+// Populations use the natural layout of two ping-pong lattices (a plain
+// push step), so that checkpoints and recomputed states are ordinary arrays.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "handle.hpp"
+#include "lattice.hpp"
+#include "lbm.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int Q = 19;
+using V = Vel<Q>;
+
+struct PorousLayout {
+  size_t state_bytes = 0;  // one population set, Q * PS floats
+  size_t fa = 0, fb = 0, ckpt = 0, seg = 0, la = 0, lb = 0, por = 0, link = 0, red = 0, total = 0;
+  int nckpt = 0;
+};
+
+PorousLayout porous_layout(size_t N, int steps, int every) {
+  PorousLayout L;
+  L.state_bytes = align256(sizeof(float) * Q * pop_stride(N));
+  L.nckpt = (steps + every - 1) / every;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.fa = take(L.state_bytes);
+  L.fb = take(L.state_bytes);
+  L.ckpt = take(L.state_bytes * (size_t)std::max(L.nckpt, 1));
+  L.seg = take(L.state_bytes * (size_t)every);
+  L.la = take(L.state_bytes);
+  L.lb = take(L.state_bytes);
+  L.por = take(sizeof(float) * N);
+  L.link = take(sizeof(uint32_t) * N);
+  L.red = take(sizeof(double) * (RED_BLOCKS + 8));
+  L.total = off;
+  return L;
+}
+
+// Collision quantities of one cell from its stored values fs_i = f_i - w_i:
+// drho = sum fs (rho = 1 + drho), j, u (force-shifted), v = d u.
+struct CellState {
+  float drho, rho, j[3], u[3], v[3];
+};
+
+__device__ __forceinline__ CellState cell_state(const float (&fs)[Q], float d, const float* g) {
+  CellState c;
+  float s = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    s += fs[i];
+    jx += (float)V::cx[i] * fs[i];
+    jy += (float)V::cy[i] * fs[i];
+    jz += (float)V::cz[i] * fs[i];
+  }
+  c.drho = s;
+  c.rho = 1.f + s;
+  c.j[0] = jx;
+  c.j[1] = jy;
+  c.j[2] = jz;
+  const float inv = 1.f / c.rho;
+  for (int a = 0; a < 3; ++a) {
+    c.u[a] = c.j[a] * inv + 0.5f * g[a];
+    c.v[a] = d * c.u[a];
+  }
+  return c;
+}
+
+// feq_i - w_i (shifted equilibrium) and the Guo term of velocity i.
+__device__ __forceinline__ void feq_and_guo(const CellState& c, float omega, const float* g,
+                                            int i, float* feqs, float* S) {
+  const float w = weight<Q, float>(i);
+  const float cv = (float)V::cx[i] * c.v[0] + (float)V::cy[i] * c.v[1] + (float)V::cz[i] * c.v[2];
+  const float vv = c.v[0] * c.v[0] + c.v[1] * c.v[1] + c.v[2] * c.v[2];
+  *feqs = w * (c.drho + c.rho * (3.f * cv + 4.5f * cv * cv - 1.5f * vv));
+  const float F[3] = {c.rho * g[0], c.rho * g[1], c.rho * g[2]};
+  const float cF = (float)V::cx[i] * F[0] + (float)V::cy[i] * F[1] + (float)V::cz[i] * F[2];
+  const float vF = c.v[0] * F[0] + c.v[1] * F[1] + c.v[2] * F[2];
+  *S = (1.f - 0.5f * omega) * w * (3.f * (cF - vF) + 9.f * cv * cF);
+}
+
+struct PorousParams {
+  float omega;
+  float g[3];
+};
+
+// Forward: collide every fluid cell of src with its porosity and push to dst
+// (wall links reflect into the cell's own opposite slot).
+__global__ void __launch_bounds__(256)
+    porous_step_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                       const float* __restrict__ por, const uint32_t* __restrict__ link, int nx,
+                       int ny, int nz, uint32_t N, uint32_t PS, PorousParams p) {
+  const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N) return;
+  const uint32_t lw = link[idx];
+  if (!(lw & LINK_FLUID)) return;
+  const int x = (int)(idx % (uint32_t)nx);
+  const int r = (int)(idx / (uint32_t)nx);
+  const Nbr nb = make_nbr(x, r % ny, r / ny, nx, ny, nz);
+  float f[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) f[i] = src[(uint32_t)i * PS + idx];
+  const CellState c = cell_state(f, por[idx], p.g);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    float feqs, S;
+    feq_and_guo(c, p.omega, p.g, i, &feqs, &S);
+    const float v = f[i] + p.omega * (feqs - f[i]) + S;
+    const bool wall = i > 0 && ((lw >> (i - 1)) & 1u);
+    const uint32_t off = wall ? (uint32_t)V::opp[i] * PS + idx
+                              : (uint32_t)i * PS + nb.at(V::cx[i], V::cy[i], V::cz[i]);
+    dst[off] = v;
+  }
+}
+
+// Adjoint of one step at state f (natural layout): pull mu from lam_next,
+// write lam_cur, accumulate the porosity gradient.
+__global__ void __launch_bounds__(256)
+    porous_adjoint_kernel(const float* __restrict__ f_t, const float* __restrict__ lam_next,
+                          float* __restrict__ lam_cur, float* __restrict__ grad,
+                          const float* __restrict__ por, const uint32_t* __restrict__ link,
+                          int nx, int ny, int nz, uint32_t N, uint32_t PS, PorousParams p) {
+  const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N) return;
+  const uint32_t lw = link[idx];
+  if (!(lw & LINK_FLUID)) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lam_cur[(uint32_t)i * PS + idx] = 0.f;
+    return;
+  }
+  const int x = (int)(idx % (uint32_t)nx);
+  const int r = (int)(idx / (uint32_t)nx);
+  const Nbr nb = make_nbr(x, r % ny, r / ny, nx, ny, nz);
+  float mu[Q], f[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const bool wall = i > 0 && ((lw >> (i - 1)) & 1u);
+    const uint32_t off = wall ? (uint32_t)V::opp[i] * PS + idx
+                              : (uint32_t)i * PS + nb.at(V::cx[i], V::cy[i], V::cz[i]);
+    mu[i] = lam_next[off];
+    f[i] = f_t[(uint32_t)i * PS + idx];
+  }
+  const float d = por[idx];
+  const CellState c = cell_state(f, d, p.g);
+  const float k = 1.f - 0.5f * p.omega;
+  const float F[3] = {c.rho * p.g[0], c.rho * p.g[1], c.rho * p.g[2]};
+  float G[3] = {0.f, 0.f, 0.f}, E = 0.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float w = weight<Q, float>(i);
+    const float ci[3] = {(float)V::cx[i], (float)V::cy[i], (float)V::cz[i]};
+    const float cv = ci[0] * c.v[0] + ci[1] * c.v[1] + ci[2] * c.v[2];
+    const float cF = ci[0] * F[0] + ci[1] * F[1] + ci[2] * F[2];
+    float feqs, S;
+    feq_and_guo(c, p.omega, p.g, i, &feqs, &S);
+    const float feq = feqs + w;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float dfeq = w * c.rho * (3.f * ci[a] + 9.f * cv * ci[a] - 3.f * c.v[a]);
+      const float dS = k * w * (-3.f * F[a] + 9.f * ci[a] * cF);
+      G[a] += mu[i] * (p.omega * dfeq + dS);
+    }
+    E += mu[i] * (p.omega * feq + S);
+  }
+  E /= c.rho;
+  grad[idx] += G[0] * c.u[0] + G[1] * c.u[1] + G[2] * c.u[2];
+  const float Arho = E - d * (G[0] * c.j[0] + G[1] * c.j[1] + G[2] * c.j[2]) / (c.rho * c.rho);
+  const float s = d / c.rho;
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    lam_cur[(uint32_t)i * PS + idx] = (1.f - p.omega) * mu[i] + Arho +
+                                      s * (G[0] * (float)V::cx[i] + G[1] * (float)V::cy[i] +
+                                           G[2] * (float)V::cz[i]);
+}
+
+// Rest state (rho = 1, u = 0: f_i = w_i), stored shifted: zero everywhere.
+__global__ void porous_init_kernel(float* __restrict__ f, uint32_t N, uint32_t PS) {
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[(uint32_t)i * PS + idx] = 0.f;
+}
+
+__global__ void fill_kernel(float* __restrict__ a, size_t n, float v) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+    a[k] = v;
+}
+
+// Objective (one block): mean of u_x over the fluid cells of plane x = px.
+__global__ void __launch_bounds__(256)
+    porous_objective_kernel(const float* __restrict__ f, const uint32_t* __restrict__ link,
+                            int px, int nx, int ny, int nz, uint32_t PS, float gx,
+                            double* __restrict__ out) {
+  __shared__ double s_sum[256];
+  __shared__ double s_cnt[256];
+  double sum = 0.0, cnt = 0.0;
+  for (int r = threadIdx.x; r < ny * nz; r += blockDim.x) {
+    const uint32_t idx = (uint32_t)px + (uint32_t)nx * (uint32_t)r;
+    if (!(link[idx] & LINK_FLUID)) continue;
+    double drho = 0.0, jx = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double v = f[(uint32_t)i * PS + idx];
+      drho += v;
+      jx += V::cx[i] * v;
+    }
+    sum += jx / (1.0 + drho) + 0.5 * gx;
+    cnt += 1.0;
+  }
+  s_sum[threadIdx.x] = sum;
+  s_cnt[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      s_sum[threadIdx.x] += s_sum[threadIdx.x + s];
+      s_cnt[threadIdx.x] += s_cnt[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = s_cnt[0] > 0 ? s_sum[0] / s_cnt[0] : 0.0;
+    out[1] = s_cnt[0];
+  }
+}
+
+// lambda^T on the objective plane: d(mean u_x)/df_i = (c_ix/rho - j_x/rho^2)/n.
+__global__ void porous_lambda_final_kernel(const float* __restrict__ f,
+                                           const uint32_t* __restrict__ link,
+                                           float* __restrict__ lam, int px, int nx, int ny,
+                                           int nz, uint32_t PS, const double* __restrict__ obj) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ny * nz) return;
+  const uint32_t idx = (uint32_t)px + (uint32_t)nx * (uint32_t)r;
+  if (!(link[idx] & LINK_FLUID)) return;
+  const float n = (float)obj[1];
+  float drho = 0.f, jx = 0.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float v = f[(uint32_t)i * PS + idx];
+    drho += v;
+    jx += (float)V::cx[i] * v;
+  }
+  const float rho = 1.f + drho;
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    lam[(uint32_t)i * PS + idx] = ((float)V::cx[i] / rho - jx / (rho * rho)) / n;
+}
+
+unsigned grid_for(size_t n, unsigned threads = 256) {
+  return (unsigned)std::max<size_t>(1, (n + threads - 1) / threads);
+}
+
+}  // namespace
+
+struct lbm_porous {
+  int nx = 0, ny = 0, nz = 0;
+  size_t N = 0, PS = 0;
+  int steps = 0, every = 0, plane_x = 0;
+  double tau = 0.0;
+  PorousParams p{};
+  unsigned char* work = nullptr;
+  PorousLayout lay;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool have_forward = false;
+  int final_buf = 0;  // 0: fa, 1: fb holds f^T
+  double J = 0.0;
+  std::string err;
+};
+
+namespace {
+
+lbm_status pfail(lbm_porous* h, lbm_status st, const std::string& msg) {
+  if (h)
+    h->err = msg;
+  else
+    lbm_detail::fail(nullptr, st, msg);
+  return st;
+}
+
+#define PHIP_TRY(h, call)                                                               \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return pfail((h), LBM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+float* fptr(lbm_porous* h, size_t off) { return (float*)(h->work + off); }
+
+void launch_step(lbm_porous* h, const float* src, float* dst) {
+  hipLaunchKernelGGL(porous_step_kernel, dim3(grid_for(h->N)), dim3(256), 0, h->stream, src, dst,
+                     fptr(h, h->lay.por), (const uint32_t*)(h->work + h->lay.link), h->nx, h->ny,
+                     h->nz, (uint32_t)h->N, (uint32_t)h->PS, h->p);
+}
+
+lbm_status check_args(int nx, int ny, int nz, int steps, int every, std::string* why) {
+  if (nx <= 0 || ny <= 0 || nz <= 0) {
+    *why = "lattice sizes must be positive";
+    return LBM_ERR_ARG;
+  }
+  if (steps < 1 || every < 1 || every > steps) {
+    *why = "need steps >= 1 and 1 <= checkpoint_every <= steps";
+    return LBM_ERR_ARG;
+  }
+  if ((double)Q * pop_stride((size_t)nx * ny * nz) >= 4294967296.0) {
+    *why = "q*N must stay below 2^32";
+    return LBM_ERR_UNSUPPORTED;
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_porous_required_bytes(int nx, int ny, int nz, int steps, int checkpoint_every,
+                                     size_t* work_bytes) {
+  std::string why;
+  lbm_status st = check_args(nx, ny, nz, steps, checkpoint_every, &why);
+  if (st) return lbm_detail::fail(nullptr, st, why);
+  if (work_bytes) *work_bytes = porous_layout((size_t)nx * ny * nz, steps, checkpoint_every).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_porous_create(lbm_porous** out, int nx, int ny, int nz, double tau,
+                             const uint8_t* material, unsigned periodic_mask, const double g[3],
+                             int steps, int checkpoint_every, int plane_x, void* dev_work,
+                             size_t work_bytes, void* hip_stream) {
+  if (!out) return lbm_detail::fail(nullptr, LBM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  lbm_status st = check_args(nx, ny, nz, steps, checkpoint_every, &why);
+  if (st) return lbm_detail::fail(nullptr, st, why);
+  if (!(std::isfinite(tau) && tau > 0.5)) return lbm_detail::fail(nullptr, LBM_ERR_ARG, "tau must be > 0.5");
+  if (!material || !g || !dev_work) return lbm_detail::fail(nullptr, LBM_ERR_ARG, "NULL argument");
+  if (plane_x < 0 || plane_x >= nx) return lbm_detail::fail(nullptr, LBM_ERR_ARG, "plane_x out of range");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(g[a])) return lbm_detail::fail(nullptr, LBM_ERR_ARG, "g must be finite");
+  const size_t N = (size_t)nx * ny * nz;
+  const PorousLayout L = porous_layout(N, steps, checkpoint_every);
+  if (work_bytes < L.total) return lbm_detail::fail(nullptr, LBM_ERR_ARG, "work buffer too small");
+  if ((uintptr_t)dev_work & 255u) return lbm_detail::fail(nullptr, LBM_ERR_ARG, "work buffer must be 256-byte aligned");
+  for (size_t i = 0; i < N; ++i)
+    if (material[i] == 3) return lbm_detail::fail(nullptr, LBM_ERR_UNSUPPORTED, "moving walls are not supported with porosity");
+  // geometry rule and link words: the same check as lbm_set_geometry
+  st = lbm_validate_geometry(LBM_D3Q19, nx, ny, nz, material, periodic_mask);
+  if (st) return st;
+  std::vector<uint32_t> link(N, 0u);
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const size_t idx = (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z);
+        if (material[idx] != 1) continue;
+        uint32_t w = LINK_FLUID;
+        for (int i = 1; i < Q; ++i) {
+          const int xn = (x + V::cx[i] + nx) % nx, yn = (y + V::cy[i] + ny) % ny,
+                    zn = (z + V::cz[i] + nz) % nz;
+          if (material[(size_t)xn + (size_t)nx * ((size_t)yn + (size_t)ny * zn)] != 1)
+            w |= 1u << (i - 1);
+        }
+        link[idx] = w;
+      }
+  lbm_porous* h = new (std::nothrow) lbm_porous();
+  if (!h) return lbm_detail::fail(nullptr, LBM_ERR_ARG, "out of host memory");
+  h->nx = nx;
+  h->ny = ny;
+  h->nz = nz;
+  h->N = N;
+  h->PS = pop_stride(N);
+  h->steps = steps;
+  h->every = checkpoint_every;
+  h->plane_x = plane_x;
+  h->tau = tau;
+  h->p.omega = (float)(1.0 / tau);
+  for (int a = 0; a < 3; ++a) h->p.g[a] = (float)g[a];
+  h->work = (unsigned char*)dev_work;
+  h->lay = L;
+  h->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&h->device) != hipSuccess ||
+      hipMemcpyAsync(h->work + L.link, link.data(), sizeof(uint32_t) * N, hipMemcpyHostToDevice,
+                     h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess) {
+    delete h;
+    return lbm_detail::fail(nullptr, LBM_ERR_HIP, "uploading the geometry failed");
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+lbm_status lbm_porous_forward(lbm_porous* h, const float* porosity_dev, double* J) {
+  if (!h) return LBM_ERR_ARG;
+  h->err.clear();
+  if (!porosity_dev || !J) return pfail(h, LBM_ERR_ARG, "NULL argument");
+  PHIP_TRY(h, hipSetDevice(h->device));
+  PHIP_TRY(h, hipMemcpyAsync(h->work + h->lay.por, porosity_dev, sizeof(float) * h->N,
+                             hipMemcpyDeviceToDevice, h->stream));
+  float* bufs[2] = {fptr(h, h->lay.fa), fptr(h, h->lay.fb)};
+  hipLaunchKernelGGL(porous_init_kernel, dim3(grid_for(h->N)), dim3(256), 0, h->stream, bufs[0],
+                     (uint32_t)h->N, (uint32_t)h->PS);
+  int cur = 0;
+  for (int t = 0; t < h->steps; ++t) {
+    if (t % h->every == 0)
+      PHIP_TRY(h, hipMemcpyAsync(h->work + h->lay.ckpt + h->lay.state_bytes * (size_t)(t / h->every),
+                                 bufs[cur], h->lay.state_bytes, hipMemcpyDeviceToDevice, h->stream));
+    launch_step(h, bufs[cur], bufs[cur ^ 1]);
+    cur ^= 1;
+  }
+  double* red = (double*)(h->work + h->lay.red);
+  hipLaunchKernelGGL(porous_objective_kernel, dim3(1), dim3(256), 0, h->stream, bufs[cur],
+                     (const uint32_t*)(h->work + h->lay.link), h->plane_x, h->nx, h->ny, h->nz,
+                     (uint32_t)h->PS, h->p.g[0], red);
+  PHIP_TRY(h, hipGetLastError());
+  double r[2];
+  PHIP_TRY(h, hipMemcpyAsync(r, red, sizeof(r), hipMemcpyDeviceToHost, h->stream));
+  PHIP_TRY(h, hipStreamSynchronize(h->stream));
+  h->final_buf = cur;
+  h->have_forward = true;
+  h->J = r[0];
+  *J = r[0];
+  if (!std::isfinite(r[0])) return pfail(h, LBM_ERR_NONFINITE, "non-finite objective");
+  return LBM_OK;
+}
+
+lbm_status lbm_porous_backward(lbm_porous* h, float* grad_dev) {
+  if (!h) return LBM_ERR_ARG;
+  h->err.clear();
+  if (!grad_dev) return pfail(h, LBM_ERR_ARG, "grad_dev is NULL");
+  if (!h->have_forward) return pfail(h, LBM_ERR_STATE, "run lbm_porous_forward first");
+  PHIP_TRY(h, hipSetDevice(h->device));
+  const uint32_t* link = (const uint32_t*)(h->work + h->lay.link);
+  const float* fT = fptr(h, h->final_buf ? h->lay.fb : h->lay.fa);
+  float* lam[2] = {fptr(h, h->lay.la), fptr(h, h->lay.lb)};
+  const size_t nstate = h->lay.state_bytes / sizeof(float);
+  hipLaunchKernelGGL(fill_kernel, dim3(1024), dim3(256), 0, h->stream, lam[0], nstate, 0.f);
+  hipLaunchKernelGGL(fill_kernel, dim3(1024), dim3(256), 0, h->stream, grad_dev, h->N, 0.f);
+  hipLaunchKernelGGL(porous_lambda_final_kernel, dim3(grid_for((size_t)h->ny * h->nz)), dim3(256),
+                     0, h->stream, fT, link, lam[0], h->plane_x, h->nx, h->ny, h->nz,
+                     (uint32_t)h->PS, (const double*)(h->work + h->lay.red));
+  int cur = 0;  // lam[cur] holds lambda^{t+1}
+  const float* por = fptr(h, h->lay.por);
+  for (int k = h->lay.nckpt - 1; k >= 0; --k) {
+    const int t0 = k * h->every;
+    const int t1 = std::min(t0 + h->every, h->steps);
+    // recompute the segment's states f^{t0} .. f^{t1-1} from its checkpoint
+    float* seg = fptr(h, h->lay.seg);
+    PHIP_TRY(h, hipMemcpyAsync(seg, h->work + h->lay.ckpt + h->lay.state_bytes * (size_t)k,
+                               h->lay.state_bytes, hipMemcpyDeviceToDevice, h->stream));
+    for (int s = 1; s < t1 - t0; ++s) launch_step(h, seg + nstate * (s - 1), seg + nstate * s);
+    for (int t = t1 - 1; t >= t0; --t) {
+      hipLaunchKernelGGL(porous_adjoint_kernel, dim3(grid_for(h->N)), dim3(256), 0, h->stream,
+                         seg + nstate * (size_t)(t - t0), lam[cur], lam[cur ^ 1], grad_dev, por,
+                         link, h->nx, h->ny, h->nz, (uint32_t)h->N, (uint32_t)h->PS, h->p);
+      cur ^= 1;
+    }
+  }
+  PHIP_TRY(h, hipGetLastError());
+  PHIP_TRY(h, hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_porous_get_final(lbm_porous* h, double* f_dev) {
+  if (!h) return LBM_ERR_ARG;
+  if (!f_dev) return pfail(h, LBM_ERR_ARG, "f_dev is NULL");
+  if (!h->have_forward) return pfail(h, LBM_ERR_STATE, "run lbm_porous_forward first");
+  PHIP_TRY(h, hipSetDevice(h->device));
+  // natural layout, FP64, dense stride N
+  std::vector<float> host(h->lay.state_bytes / sizeof(float));
+  PHIP_TRY(h, hipMemcpyAsync(host.data(), h->work + (h->final_buf ? h->lay.fb : h->lay.fa),
+                             h->lay.state_bytes, hipMemcpyDeviceToHost, h->stream));
+  PHIP_TRY(h, hipStreamSynchronize(h->stream));
+  std::vector<double> dense((size_t)Q * h->N);
+  std::vector<uint32_t> link(h->N);
+  PHIP_TRY(h, hipMemcpyAsync(link.data(), h->work + h->lay.link, sizeof(uint32_t) * h->N,
+                             hipMemcpyDeviceToHost, h->stream));
+  PHIP_TRY(h, hipStreamSynchronize(h->stream));
+  for (int i = 0; i < Q; ++i)
+    for (size_t idx = 0; idx < h->N; ++idx)
+      dense[(size_t)i * h->N + idx] =
+          (link[idx] & LINK_FLUID) ? (double)host[(size_t)i * h->PS + idx] + Vel<Q>::w36[i] / 36.0 : 0.0;
+  PHIP_TRY(h, hipMemcpyAsync(f_dev, dense.data(), sizeof(double) * dense.size(),
+                             hipMemcpyHostToDevice, h->stream));
+  PHIP_TRY(h, hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_porous_destroy(lbm_porous* h) {
+  if (!h) return LBM_ERR_ARG;
+  hipError_t e = hipSetDevice(h->device);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  delete h;
+  return e == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+const char* lbm_porous_last_error(const lbm_porous* h) { return h ? h->err.c_str() : ""; }
+
+}  // extern "C"
