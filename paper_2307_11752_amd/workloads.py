@@ -84,6 +84,25 @@ def tgv_ensemble(count=256, seed=1107, lmin=16, lmax=96, u0_range=(0.01, 0.08),
     return shapes, u0, tau
 
 
+def porous_channel(nx=128, ny=64, nz=64, seed=4668, sigma=4.0):
+    """Channel for porosity gradients: periodic along x, resting walls on the
+    outer y and z layers, porosity = seeded white noise smoothed by a Gaussian
+    of sigma cells (periodic along x), min-max mapped to [0, 1].
+    Returns (material (nz, ny, nx) uint8, porosity (nz, ny, nx) float64)."""
+    from scipy.ndimage import gaussian_filter
+
+    rng = np.random.default_rng(seed)
+    mat = np.ones((nz, ny, nx), np.uint8)
+    mat[:, 0, :] = 2
+    mat[:, -1, :] = 2
+    mat[0, :, :] = 2
+    mat[-1, :, :] = 2
+    noise = rng.standard_normal((nz, ny, nx))
+    smooth = gaussian_filter(noise, sigma, mode=("nearest", "nearest", "wrap"))
+    por = (smooth - smooth.min()) / (smooth.max() - smooth.min())
+    return mat, por
+
+
 def channel_spheres(nx=512, ny=128, nz=128, seed=2307, solid_fraction=0.20, rmin=4.0,
                     rmax=10.0, g=1e-6, tau=0.7, steps=5000, storage="f32"):
     """Body-force-driven channel: periodic along x, resting walls on the outer y
