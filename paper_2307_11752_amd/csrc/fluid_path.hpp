@@ -19,6 +19,7 @@
 namespace lbm {
 
 typedef uint32_t raw8 __attribute__((ext_vector_type(2)));
+typedef uint32_t raw16 __attribute__((ext_vector_type(4)));
 
 template <int BYTES>
 struct RawOf;
@@ -33,6 +34,10 @@ struct RawOf<4> {
 template <>
 struct RawOf<8> {
   using type = raw8;
+};
+template <>
+struct RawOf<16> {
+  using type = raw16;
 };
 
 // C consecutive values of storage type S as one machine word.
@@ -50,6 +55,47 @@ struct Lane {
 
 template <typename S>
 using Pack8 = Lane<S, 8 / (int)sizeof(S)>;
+
+// A lane's word at a uniform base plus a 32-bit byte offset.  Offsets inside
+// one population array always fit (q * N < 2^32 elements), and this form lets
+// the hardware add a scalar base to a 32-bit vector offset instead of holding
+// one 64-bit address per direction in vector registers.
+// (The base passes through readfirstlane so that the compiler keeps it apart
+// from the vector offset; it must be the same in every lane.)
+template <typename R>
+using global_ptr = __attribute__((address_space(1))) R*;
+
+template <typename R, typename S>
+__device__ __forceinline__ global_ptr<R> at_byte(const S* base, uint32_t byte_off) {
+  const uint64_t b = (uint64_t)base;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+  return (global_ptr<R>)((__attribute__((address_space(1))) char*)(((uint64_t)hi << 32) | lo) + byte_off);
+}
+
+// One population value at element idx of the array at (uniform) base, in the
+// compute type; NT selects a non-temporal access.
+template <typename S, bool NT>
+__device__ __forceinline__ typename Store<S>::T elem_load(const S* base, uint32_t idx) {
+  using U = typename RawOf<(int)sizeof(S)>::type;
+  const global_ptr<U> q = at_byte<U>(base, idx * (uint32_t)sizeof(S));
+  const U u = NT ? __builtin_nontemporal_load(q) : *q;
+  S v;
+  __builtin_memcpy(&v, &u, sizeof(S));
+  return Store<S>::cvt(v);
+}
+template <typename S, bool NT>
+__device__ __forceinline__ void elem_store(S* base, uint32_t idx, typename Store<S>::T v) {
+  using U = typename RawOf<(int)sizeof(S)>::type;
+  const S s = Store<S>::pack(v);
+  U u;
+  __builtin_memcpy(&u, &s, sizeof(S));
+  const global_ptr<U> q = at_byte<U>(base, idx * (uint32_t)sizeof(S));
+  if (NT)
+    __builtin_nontemporal_store(u, q);
+  else
+    *q = u;
+}
 
 template <int Q>
 struct Shifted {
@@ -75,10 +121,12 @@ __device__ __forceinline__ void fluid_cells_p0(S* __restrict__ pop, uint32_t PS,
   using T = typename Store<S>::T;
   using V = Vel<Q>;
   using L = Lane<S, C>;
+  using R = typename L::raw;
+  const uint32_t lo = c0 * (uint32_t)sizeof(S);
   S sv[Q][C];
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    L::unpack(__builtin_nontemporal_load((const typename L::raw*)(pop + (uint32_t)i * PS + c0)), sv[i]);
+    L::unpack(__builtin_nontemporal_load(at_byte<R>(pop + (size_t)i * PS, lo)), sv[i]);
 #pragma unroll
   for (int k = 0; k < C; ++k) {
     T f[Q];
@@ -87,10 +135,11 @@ __device__ __forceinline__ void fluid_cells_p0(S* __restrict__ pop, uint32_t PS,
     collide<Q, SHIFT, T>(f, p);
 #pragma unroll
     for (int i = 0; i < Q; ++i) sv[V::opp[i]][k] = Store<S>::pack(f[i]);
+    __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    __builtin_nontemporal_store(L::pack(sv[i]), (typename L::raw*)(pop + (uint32_t)i * PS + c0));
+    __builtin_nontemporal_store(L::pack(sv[i]), at_byte<R>(pop + (size_t)i * PS, lo));
 }
 
 // Phase 1 of x-row `row` (= y + ny z) of a fully fluid periodic lattice, lane
@@ -110,13 +159,13 @@ __device__ __forceinline__ void fluid_rows_p1(S* __restrict__ pop, int nx, int n
   const int Z[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
   const int x0 = C * t;
 
+  using R = typename L::raw;
   S sv[Q][C];
   if (active) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const int o = V::opp[i];
-      const uint32_t base = (uint32_t)o * PS + (uint32_t)nx * (uint32_t)(Y[1 - V::cy[i]] + ny * Z[1 - V::cz[i]]);
-      const typename L::raw r = __builtin_nontemporal_load((const typename L::raw*)(pop + base + x0));
+      const uint32_t off = (uint32_t)nx * (uint32_t)(Y[1 - V::cy[i]] + ny * Z[1 - V::cz[i]]) + x0;
+      const R r = __builtin_nontemporal_load(at_byte<R>(pop + (size_t)V::opp[i] * PS, off * (uint32_t)sizeof(S)));
       if (V::cx[i] == 0)
         L::unpack(r, sv[i]);
       else
@@ -150,8 +199,8 @@ __device__ __forceinline__ void fluid_rows_p1(S* __restrict__ pop, int nx, int n
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       if (V::cx[i] == 0) {
-        const uint32_t base = (uint32_t)i * PS + (uint32_t)nx * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]);
-        __builtin_nontemporal_store(L::pack(sv[i]), (typename L::raw*)(pop + base + x0));
+        const uint32_t off = (uint32_t)nx * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]) + x0;
+        __builtin_nontemporal_store(L::pack(sv[i]), at_byte<R>(pop + (size_t)i * PS, off * (uint32_t)sizeof(S)));
       } else {
 #pragma unroll
         for (int k = 0; k < C; ++k) {
@@ -167,10 +216,96 @@ __device__ __forceinline__ void fluid_rows_p1(S* __restrict__ pop, int nx, int n
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       if (V::cx[i] == 0) continue;
-      const uint32_t base = (uint32_t)i * PS + (uint32_t)nx * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]);
-      __builtin_nontemporal_store(*(const typename L::raw*)(tile + Shifted<Q>::rank(i) * nx + x0),
-                                  (typename L::raw*)(pop + base + x0));
+      const uint32_t off = (uint32_t)nx * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]) + x0;
+      __builtin_nontemporal_store(*(const R*)(tile + Shifted<Q>::rank(i) * nx + x0),
+                                  at_byte<R>(pop + (size_t)i * PS, off * (uint32_t)sizeof(S)));
     }
+  }
+}
+
+// One value taken from lane `src` of the wave (ds_bpermute; every lane of the
+// wave that reaches this call takes part).
+template <typename S>
+__device__ __forceinline__ S lane_take(S v, int src) {
+  static_assert(sizeof(S) == 2 || sizeof(S) == 4 || sizeof(S) == 8, "element size");
+  constexpr int W = sizeof(S) == 8 ? 2 : 1;
+  uint32_t w[W] = {};
+  __builtin_memcpy(w, &v, sizeof(S));
+#pragma unroll
+  for (int j = 0; j < W; ++j) w[j] = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)w[j]);
+  S r;
+  __builtin_memcpy(&r, w, sizeof(S));
+  return r;
+}
+
+// v[k] <- the row's element k - s (s = +1 or -1) for a lane holding C
+// consecutive cells of an x-row: the element that crosses into this lane
+// comes from lane `left` (s = +1) or `right` (s = -1), the lanes holding the
+// preceding and following cells (periodic within the row).
+template <typename S, int C>
+__device__ __forceinline__ void shift_along_row(S (&v)[C], int s, int left, int right) {
+  if (s > 0) {
+    const S edge = lane_take(v[C - 1], left);
+#pragma unroll
+    for (int k = C - 1; k > 0; --k) v[k] = v[k - 1];
+    v[0] = edge;
+  } else {
+    const S edge = lane_take(v[0], right);
+#pragma unroll
+    for (int k = 0; k < C - 1; ++k) v[k] = v[k + 1];
+    v[C - 1] = edge;
+  }
+}
+
+// Phase 1 of x-row `row` (= y + ny z) of a fully fluid periodic lattice held
+// by nx / C lanes of one wave, lane t covering cells x = C t .. C t + C - 1
+// (`left` / `right`: the lanes holding row positions t - 1 and t + 1, wrapped).
+// Every access is an aligned, non-temporal row segment; populations with
+// c_x != 0 move one cell between lanes in registers after loading and before
+// storing, so no LDS tile and no barrier is needed.
+template <int Q, typename S, bool SHIFT, int C>
+__device__ __forceinline__ void fluid_rows_p1_wave(S* __restrict__ pop, int nx, int ny, int nz,
+                                                   uint32_t PS, int row, int t, int left,
+                                                   int right,
+                                                   const StepParams<typename Store<S>::T>& p) {
+  using T = typename Store<S>::T;
+  using V = Vel<Q>;
+  using L = Lane<S, C>;
+  const int y = row % ny;
+  const int z = row / ny;
+  const int Y[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
+  const int Z[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
+  using R = typename L::raw;
+  const uint32_t x0 = (uint32_t)(C * t);
+
+  // incoming: f_i(x) = A[opp(i)][x - c_i]
+  S sv[Q][C];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const uint32_t r = (uint32_t)nx * (uint32_t)(Y[1 - V::cy[i]] + ny * Z[1 - V::cz[i]]);
+    L::unpack(__builtin_nontemporal_load(at_byte<R>(pop + (size_t)V::opp[i] * PS, (r + x0) * (uint32_t)sizeof(S))), sv[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    if (V::cx[i] != 0) shift_along_row<S, C>(sv[i], V::cx[i], left, right);
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    T f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = Store<S>::cvt(sv[i][k]);
+    collide<Q, SHIFT, T>(f, p);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) sv[i][k] = Store<S>::pack(f[i]);
+    // one cell at a time: interleaving the C collisions only raises register
+    // pressure (and lowers occupancy) in a kernel bound by memory
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // outgoing: A[i][x + c_i] = f*_i(x)
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (V::cx[i] != 0) shift_along_row<S, C>(sv[i], V::cx[i], left, right);
+    const uint32_t r = (uint32_t)nx * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]);
+    __builtin_nontemporal_store(L::pack(sv[i]), at_byte<R>(pop + (size_t)i * PS, (r + x0) * (uint32_t)sizeof(S)));
   }
 }
 

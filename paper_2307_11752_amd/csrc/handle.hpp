@@ -72,6 +72,7 @@ struct lbm_lattice {
   long long steps = 0;
   long long nfluid = 0;
   int bx = 256, nxb = 1;
+  int lds_per_cu = 0;  // bytes of LDS per compute unit (occupancy caps)
   // Replay of a captured run of graph_steps steps (0 = direct launches).  The
   // graph bakes in the kernel arguments, so any parameter change drops it.
   int graph_steps = 0;

@@ -92,12 +92,10 @@ struct Store<_Float16> {
   static __device__ __forceinline__ _Float16 pack(T v) { return (_Float16)v; }
 };
 
-// bfloat16: the upper half of an IEEE single; float -> bf16 rounds to nearest even.
+// bfloat16: the upper half of an IEEE single; float -> bf16 rounds to nearest
+// even (gfx950 converts in hardware, v_cvt_pk_bf16_f32, two values at a time).
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float v) {
-  uint32_t u = __float_as_uint(v);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)v);
 }
 
 template <>
@@ -193,24 +191,25 @@ __device__ __forceinline__ T collide(T (&f)[Q], const StepParams<T>& p) {
   const T uu = ux * ux + uy * uy + uz * uz;
   const T A = sf - T(1.5) * rho * uu;
   const T om = p.omega;
-  T Fx = T(0), Fy = T(0), Fz = T(0), kuF = T(0);
-  if (p.has_force) {
-    Fx = rho * p.g[0];
-    Fy = rho * p.g[1];
-    Fz = rho * p.g[2];
-    kuF = ux * Fx + uy * Fy + uz * Fz;
-  }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const T w = weight<Q, T>(i);
     const T cu = T(V::cx[i]) * ux + T(V::cy[i]) * uy + T(V::cz[i]) * uz;
     const T feq = w * (A + rho * cu * (T(3) + T(4.5) * cu));
-    T v = f[i] + om * (feq - f[i]);
-    if (p.has_force) {
+    f[i] = f[i] + om * (feq - f[i]);
+  }
+  // The Guo source is added in a block of its own behind a uniform branch, so
+  // that unforced lattices skip it instead of computing and discarding it.
+  if (p.has_force) {
+    const T Fx = rho * p.g[0], Fy = rho * p.g[1], Fz = rho * p.g[2];
+    const T kuF = ux * Fx + uy * Fy + uz * Fz;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const T w = weight<Q, T>(i);
+      const T cu = T(V::cx[i]) * ux + T(V::cy[i]) * uy + T(V::cz[i]) * uz;
       const T cF = T(V::cx[i]) * Fx + T(V::cy[i]) * Fy + T(V::cz[i]) * Fz;
-      v += p.kguo * w * (T(3) * (cF - kuF) + T(9) * cu * cF);
+      f[i] += p.kguo * w * (T(3) * (cF - kuF) + T(9) * cu * cF);
     }
-    f[i] = v;
   }
   return rho;
 }

@@ -60,6 +60,7 @@ __global__ void __launch_bounds__(256)
   const uint32_t idx = (uint32_t)x + (uint32_t)nx * (uint32_t)(y + ny * z);
 
   const Nbr nb = make_nbr(x, y, z, nx, ny, nz);
+  const uint32_t PS = N;  // population stride
   uint32_t lw = LINK_FLUID, mv = 0;
   T f[Q];
   if (MASKED && PHASE == 1) {
@@ -70,14 +71,15 @@ __global__ void __launch_bounds__(256)
     lw = link[idx];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const uint32_t off = (uint32_t)V::opp[i] * N + nb.at(-V::cx[i], -V::cy[i], -V::cz[i]);
-      f[i] = V::cx[i] == 0 ? load_nt<S>(pop + off) : Store<S>::load(pop + off);
+      const S* a = pop + (size_t)V::opp[i] * PS;
+      const uint32_t k = nb.at(-V::cx[i], -V::cy[i], -V::cz[i]);
+      f[i] = V::cx[i] == 0 ? elem_load<S, true>(a, k) : elem_load<S, false>(a, k);
     }
     if (!(lw & LINK_FLUID)) return;
     if (p.has_moving && (lw & LINK_HAS_MOVING)) mv = mov[idx];
 #pragma unroll
     for (int i = 1; i < Q; ++i)
-      if ((lw >> (V::opp[i] - 1)) & 1u) f[i] = Store<S>::load(pop + (uint32_t)i * N + idx);
+      if ((lw >> (V::opp[i] - 1)) & 1u) f[i] = elem_load<S, false>(pop + (size_t)i * PS, idx);
   } else {
     if (MASKED) {
       lw = link[idx];
@@ -86,18 +88,15 @@ __global__ void __launch_bounds__(256)
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      uint32_t off;
-      if (PHASE == 0)
-        off = (uint32_t)i * N + idx;
-      else
-        off = (uint32_t)V::opp[i] * N + nb.at(-V::cx[i], -V::cy[i], -V::cz[i]);
       // Streaming data is touched once per launch: x-aligned accesses bypass
       // the caches; x-shifted ones (phase 1, c_x != 0) share lines with the
       // neighbouring wave and stay cached.
-      if (PHASE == 0 || V::cx[i] == 0)
-        f[i] = load_nt<S>(pop + off);
+      if (PHASE == 0)
+        f[i] = elem_load<S, true>(pop + (size_t)i * PS, idx);
+      else if (V::cx[i] == 0)
+        f[i] = elem_load<S, true>(pop + (size_t)V::opp[i] * PS, nb.at(0, -V::cy[i], -V::cz[i]));
       else
-        f[i] = Store<S>::load(pop + off);
+        f[i] = elem_load<S, false>(pop + (size_t)V::opp[i] * PS, nb.at(-V::cx[i], -V::cy[i], -V::cz[i]));
     }
   }
 
@@ -107,17 +106,15 @@ __global__ void __launch_bounds__(256)
   for (int i = 0; i < Q; ++i) {
     T v = f[i];
     if (MASKED && i > 0 && ((mv >> (i - 1)) & 1u)) v -= rho * p.mw[i];
-    uint32_t off;
     if (PHASE == 0) {
-      off = (uint32_t)V::opp[i] * N + idx;
+      elem_store<S, true>(pop + (size_t)V::opp[i] * PS, idx, v);
+    } else if (MASKED && i > 0 && ((lw >> (i - 1)) & 1u)) {
+      elem_store<S, false>(pop + (size_t)V::opp[i] * PS, idx, v);
+    } else if (V::cx[i] == 0) {
+      elem_store<S, true>(pop + (size_t)i * PS, nb.at(0, V::cy[i], V::cz[i]), v);
     } else {
-      off = (uint32_t)i * N + nb.at(V::cx[i], V::cy[i], V::cz[i]);
-      if (MASKED && i > 0 && ((lw >> (i - 1)) & 1u)) off = (uint32_t)V::opp[i] * N + idx;
+      elem_store<S, false>(pop + (size_t)i * PS, nb.at(V::cx[i], V::cy[i], V::cz[i]), v);
     }
-    if (PHASE == 0 || V::cx[i] == 0)
-      store_nt<S>(pop + off, v);
-    else
-      Store<S>::store(pop + off, v);
   }
 }
 
@@ -133,11 +130,10 @@ __global__ void __launch_bounds__(256)
 // LDS and stored aligned.  This removes the misaligned accesses that
 // otherwise cost about 12 % of bandwidth in this phase.
 // ---------------------------------------------------------------------------
-template <int Q, typename S, bool SHIFT>
+template <int Q, typename S, bool SHIFT, int C>
 __global__ void __launch_bounds__(256)
     step_p0_flat_kernel(S* __restrict__ pop, uint32_t N, uint32_t PS,
                         StepParams<typename Store<S>::T> p) {
-  constexpr int C = Pack8<S>::C;
   const uint32_t c0 = (uint32_t)C * (blockIdx.x * blockDim.x + threadIdx.x);
   if (c0 >= N) return;
   fluid_cells_p0<Q, S, SHIFT, C>(pop, PS, c0, p);
@@ -154,6 +150,33 @@ __global__ void __launch_bounds__(256)
   const int row = (int)blockIdx.x * rows_per_block + rloc;
   S* tile = (S*)smem_raw + (size_t)rloc * Shifted<Q>::count() * nx;
   fluid_rows_p1<Q, S, SHIFT, C>(pop, nx, ny, nz, N, row, row < ny * nz, t, tile, p);
+}
+
+// Phase 1 with each x-row held by 2^lr_log2 = nx / C lanes of one wave (a
+// power of two up to 64, so a wave covers 64 / 2^lr_log2 whole rows).  No LDS
+// and no barrier: the x-shifted populations move between lanes in registers.
+// ONE_ROW (nx = 64 C): the wave's row is uniform, so every row address is
+// scalar and the lanes only carry their x offset.
+template <int Q, typename S, bool SHIFT, int C, bool ONE_ROW>
+__global__ void __launch_bounds__(256)
+    step_p1_wave_kernel(S* __restrict__ pop, int nx, int ny, int nz, uint32_t PS, int lr_log2,
+                        StepParams<typename Store<S>::T> p) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if constexpr (ONE_ROW) {
+    const int row = __builtin_amdgcn_readfirstlane(wave);
+    if (row >= ny * nz) return;
+    fluid_rows_p1_wave<Q, S, SHIFT, C>(pop, nx, ny, nz, PS, row, lane, (lane - 1) & 63,
+                                       (lane + 1) & 63, p);
+  } else {
+    const int lr = 1 << lr_log2;
+    const int t = lane & (lr - 1);
+    const int first = lane - t;
+    const int row = (wave << (6 - lr_log2)) + (lane >> lr_log2);
+    if (row >= ny * nz) return;  // whole rows drop out together
+    fluid_rows_p1_wave<Q, S, SHIFT, C>(pop, nx, ny, nz, PS, row, t, first + ((t - 1) & (lr - 1)),
+                                       first + ((t + 1) & (lr - 1)), p);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -199,10 +222,11 @@ __global__ void __launch_bounds__(256)
   // before issuing the population loads would expose one memory latency per wave
   uint32_t lw[C];
   LinkVec<C>::load(link + c0, lw);
+  const uint32_t lo = c0 * (uint32_t)sizeof(S);
   S sv[Q][C];
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    Pack8<S>::unpack(__builtin_nontemporal_load((const raw8*)(pop + (uint32_t)i * PS + c0)), sv[i]);
+    Pack8<S>::unpack(__builtin_nontemporal_load(at_byte<raw8>(pop + (size_t)i * PS, lo)), sv[i]);
 #pragma unroll
   for (int k = 0; k < C; ++k) {
     if (!(lw[k] & LINK_FLUID)) continue;
@@ -220,7 +244,7 @@ __global__ void __launch_bounds__(256)
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    __builtin_nontemporal_store(Pack8<S>::pack(sv[i]), (raw8*)(pop + (uint32_t)i * PS + c0));
+    __builtin_nontemporal_store(Pack8<S>::pack(sv[i]), at_byte<raw8>(pop + (size_t)i * PS, lo));
 }
 
 // ---------------------------------------------------------------------------
@@ -570,12 +594,52 @@ StepParams<T> make_params(const lbm_lattice* h) {
   return p;
 }
 
+// Dynamic LDS that caps a launch at `blocks_per_cu` resident blocks per
+// compute unit (and at least `need` bytes, the kernel's own tile).  The
+// streaming kernels run faster with fewer resident waves than their register
+// use allows: each wave keeps 2 q row segments of different arrays in flight,
+// and more of them only spread HBM accesses over more DRAM pages.  The counts
+// used below were measured on MI355X (160 KiB of LDS per CU).
+inline size_t occupancy_lds(const lbm_lattice* h, int blocks_per_cu, size_t need) {
+  if (blocks_per_cu <= 0 || h->lds_per_cu <= 0) return need;
+  const size_t cap = (size_t)(h->lds_per_cu / blocks_per_cu) & ~(size_t)1023;
+  return (cap > need && cap <= 65536) ? cap : need;
+}
+
+// log2(nx / c) when an x-row splits into a power of two of at most 64 lanes of
+// c cells each (one wave then holds whole rows), else -1.
+inline int wave_row_log2(int nx, int c) {
+  if (c < 1 || nx % c != 0) return -1;
+  const int lr = nx / c;
+  if (lr > 64 || (lr & (lr - 1)) != 0) return -1;
+  int l = 0;
+  while ((1 << l) < lr) ++l;
+  return l;
+}
+
 // ---------------------------------------------------------------------------
 // Typed dispatch
 // ---------------------------------------------------------------------------
 template <int Q, typename S, bool SHIFT>
 struct Ops {
   using T = typename Store<S>::T;
+
+  static void launch_p1_wave(lbm_lattice* h, S* pop, uint32_t PS, int lrw, const StepParams<T>& p) {
+    if constexpr (sizeof(S) == 2) {
+      constexpr int C = Pack8<S>::C;
+      const unsigned threads = 128;
+      const size_t lds = occupancy_lds(h, 4, 0);
+      const size_t rows = (size_t)h->ny * h->nz;
+      const size_t waves = (rows + (64 >> lrw) - 1) / (64 >> lrw);
+      const unsigned nb = (unsigned)((waves * 64 + threads - 1) / threads);
+      if (lrw == 6)
+        hipLaunchKernelGGL((step_p1_wave_kernel<Q, S, SHIFT, C, true>), dim3(nb), dim3(threads), lds,
+                           h->stream, pop, h->nx, h->ny, h->nz, PS, lrw, p);
+      else
+        hipLaunchKernelGGL((step_p1_wave_kernel<Q, S, SHIFT, C, false>), dim3(nb), dim3(threads),
+                           lds, h->stream, pop, h->nx, h->ny, h->nz, PS, lrw, p);
+    }
+  }
 
   static void step(lbm_lattice* h, int phase) {
     const StepParams<T> p = make_params<T>(h);
@@ -585,29 +649,40 @@ struct Ops {
     const dim3 grid((unsigned)(h->nxb * h->ny * h->nz)), block((unsigned)h->bx);
     const uint32_t N = (uint32_t)h->N;
     const uint32_t PS = (uint32_t)h->ps;
-    constexpr int C = Pack8<S>::C;
+    constexpr int C = Pack8<S>::C;  // cells per 8-byte lane
     const int tpr = h->nx / C;
-    if (h->all_fluid && h->nx % C == 0 && tpr <= 256) {
+    // 16-bit storage: rows of nx = 4 * 2^k <= 256 cells fit one wave
+    const int lrw = sizeof(S) == 2 ? wave_row_log2(h->nx, C) : -1;
+    if (h->all_fluid && (lrw >= 0 || (h->nx % C == 0 && tpr <= 256))) {
+      // fully fluid fast path (measured launch shapes): phase 0 over flat
+      // cell ranges, 256 threads, three blocks per CU; phase 1 on whole rows,
+      // one wave per row for 16-bit storage (128 threads, four blocks per CU),
+      // else through the LDS row tile (three blocks per CU)
       if (phase == 0) {
-        const unsigned threads = 128;
+        const unsigned threads = 256;
         const unsigned nb = (unsigned)((h->N / C + threads - 1) / threads);
-        hipLaunchKernelGGL((step_p0_flat_kernel<Q, S, SHIFT>), dim3(nb), dim3(threads), 0,
-                           h->stream, pop, N, PS, p);
+        hipLaunchKernelGGL((step_p0_flat_kernel<Q, S, SHIFT, C>), dim3(nb), dim3(threads),
+                           occupancy_lds(h, 3, 0), h->stream, pop, N, PS, p);
+      } else if (lrw >= 0) {
+        launch_p1_wave(h, pop, PS, lrw, p);
       } else {
         const int rpb = tpr >= 256 ? 1 : 256 / tpr;
         const int rows = h->ny * h->nz;
         const unsigned nb = (unsigned)((rows + rpb - 1) / rpb);
         const size_t lds = (size_t)rpb * Shifted<Q>::count() * h->nx * sizeof(S);
-        hipLaunchKernelGGL((step_p1_rows_kernel<Q, S, SHIFT>), dim3(nb), dim3(rpb * tpr), lds,
-                           h->stream, pop, h->nx, h->ny, h->nz, PS, tpr, rpb, p);
+        hipLaunchKernelGGL((step_p1_rows_kernel<Q, S, SHIFT>), dim3(nb), dim3(rpb * tpr),
+                           occupancy_lds(h, 3, lds), h->stream, pop, h->nx, h->ny, h->nz, PS, tpr,
+                           rpb, p);
       }
     } else if (!h->all_fluid && h->N % C == 0 && h->N >= 65536 && phase == 0) {
       // (small lattices are latency-bound: the per-cell kernel below, with
-      // more and smaller blocks, is faster there)
+      // more and smaller blocks, is faster there).  Four blocks per CU for
+      // 4- and 8-byte storage (measured); 16-bit storage gains nothing from a cap.
       const unsigned threads = 128;
       const unsigned nb = (unsigned)((h->N / C + threads - 1) / threads);
-      hipLaunchKernelGGL((step_p0_masked_kernel<Q, S, SHIFT>), dim3(nb), dim3(threads), 0,
-                         h->stream, pop, link, mov, N, PS, p);
+      hipLaunchKernelGGL((step_p0_masked_kernel<Q, S, SHIFT>), dim3(nb), dim3(threads),
+                         occupancy_lds(h, sizeof(S) >= 4 ? 4 : 0, 0), h->stream, pop, link, mov, N,
+                         PS, p);
     } else if (h->all_fluid) {
       if (phase == 0)
         hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 0, false>), grid, block, 0, h->stream, pop,
@@ -782,9 +857,12 @@ lbm_status lbm_lattice_create(lbm_lattice** out, lbm_descriptor d, int nx, int n
   h->bx = nx >= 256 ? 256 : ((nx + 63) / 64) * 64;
   h->nxb = (nx + h->bx - 1) / h->bx;
   hipError_t e = hipGetDevice(&h->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&h->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                              h->device);
   if (e != hipSuccess) {
     delete h;
-    return fail(nullptr, LBM_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    return fail(nullptr, LBM_ERR_HIP, std::string("device query: ") + hipGetErrorString(e));
   }
   *out = h;
   return LBM_OK;
