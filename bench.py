@@ -365,8 +365,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md, 'More than one GPU'); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: no multi-GPU path is implemented "
+              "(the slab decomposition is a design, not code); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "ensemble":

@@ -1,12 +1,16 @@
 """GPU parity: the gfx950 path (through the C ABI) against the FP64 oracle on
 the same seeded inputs.
 
-Bars (derived in DESIGN.md, section "Parity bars"):
+Bars, each from the arithmetic of the step:
 * pure streaming (omega = 0, g = 0, u_w = 0), any storage, odd and even step
-  counts: bit-exact;
-* FP64 storage, full steps with forcing and moving walls: max |df| <= 1e-13;
+  counts: bit-exact (a permutation of stored values);
+* FP64 storage, full steps with forcing and moving walls: max |df| <= 1e-13
+  (~30 flops per population per step at 2^-53 on values <= 0.5, FMA
+  contraction on the GPU only, <= 20 steps: ~1e-14, with a factor 10 margin);
 * one step from an exactly representable state, any storage: every population
-  within one storage ulp plus 64 compute-type eps of its weight;
+  within one storage ulp plus 64 compute-type eps of its weight (rounding to
+  storage <= 1/2 ulp, a tie may go either way, ~10 eps * w of collision
+  arithmetic);
 * FP32 storage, many steps: velocity rel-L2 <= 1e-5 (100 steps);
 * moments / totals of a state equal the oracle's of the same state to FP64
   rounding.
