@@ -24,6 +24,44 @@ METRIC = "MLUPS & HBM GB/s (% peak), D3Q19 BGK 256³; FP16-store vs FP32 at stat
 HBM_PEAK_GBS = 8000.0
 STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
+# Sources each kernel family is compiled from: a measured HBM traffic figure
+# (profiles/hbm_traffic.json, from rocprofv3 FETCH_SIZE / WRITE_SIZE) is
+# reported only while these files are unchanged since it was taken.
+_CSRC = os.path.join("paper_2307_11752_amd", "csrc")
+KERNEL_SOURCES = {
+    "lattice": [os.path.join(_CSRC, n) for n in ("lbm.hip", "lattice.hpp", "fluid_path.hpp",
+                                                  "handle.hpp")] + ["include/lbm.h"],
+    "batch": [os.path.join(_CSRC, n) for n in ("batch.hip", "lattice.hpp", "fluid_path.hpp",
+                                                "handle.hpp")] + ["include/lbm.h"],
+    "porous": [os.path.join(_CSRC, n) for n in ("adjoint.hip", "lattice.hpp", "handle.hpp")]
+    + ["include/lbm.h"],
+}
+TRAFFIC_FILE = os.path.join("profiles", "hbm_traffic.json")
+
+
+def sources_sha256(kind):
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key, kind):
+    """HBM bytes per launch measured by rocprofv3 for workload `key`, or None
+    when there is no measurement or the kernel sources changed since."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    e = table.get("entries", {}).get(key)
+    if not e or e.get("sources_sha256") != sources_sha256(kind):
+        return None
+    return e["traffic_bytes_per_launch"]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -40,9 +78,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-steps", type=int, default=0,
                     help="run exactly this many oracle steps (overrides --cpu-seconds)")
-    ap.add_argument("--variants", default="",
-                    help="comma list of storages compared with the oracle after the oracle's "
-                         "steps: f64, f32, f32s, f16s, bf16s (s = weight-shifted)")
+    ap.add_argument("--variants", default=None,
+                    help="comma list of further storages, each timed like the main one and "
+                         "compared with the oracle after the oracle's steps: f64, f32, f32s, "
+                         "f16s, bf16s (s = weight-shifted); default for tgv3d: f16s,bf16s")
     ap.add_argument("--ref-steps", type=int, default=0,
                     help="also run the FP64-storage GPU path (parity-tested against the oracle) "
                          "for this many steps and state every --variants storage's error "
@@ -240,9 +279,12 @@ def bench_ensemble(args):
                    "graph_steps": args.graph_steps},
         "kernel_ms_per_step": round(kernel_ms, 5),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(
+                         f"ensemble/{storage}{'-shifted' if shifted else ''}", "batch"),
                      "algorithmic_bytes_per_launch": alg_bytes,
-                     "kernel": f"batch_step_kernel<Q=19,{storage}>"},
+                     "kernel": f"batch_step_kernel<Q=19,{storage}> phase 0 + phase 1, one launch "
+                               "per step alternating, averaged over both"},
         "cpu_baseline": cpu,
         "oracle_parity": parity,
         "unbatched_mlups": round(unbatched, 2),
@@ -352,8 +394,11 @@ def bench_adjoint(args):
         "value_note": "lattice updates (forward + recomputed + adjoint) per second of one "
                       "gradient evaluation",
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "algorithmic_bytes_per_launch": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("adjoint/f32-shifted", "porous"),
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "launch_unit": "one gradient evaluation: every porous_step_kernel and "
+                                    "porous_adjoint_kernel launch of it",
                      "kernel": "porous_step_kernel + porous_adjoint_kernel (whole gradient)"},
         "cpu_baseline": cpu,
         "oracle_check": check,
@@ -397,9 +442,44 @@ def main():
             lt.set_graph_steps(args.graph_steps)
         return lt
 
+    if args.variants is None:
+        args.variants = "f16s,bf16s" if args.workload == "tgv3d" else ""
     lat = make_lattice(storage, shifted)
     _, nfluid = lat.info()
     masked = nfluid != N
+    def kernel_label(st):
+        if masked:
+            return (f"step_p0_masked_kernel + step_kernel<masked> (Q={q}, {st}), one launch per "
+                    "step alternating, averaged over both")
+        p1 = ("step_p1_wave_kernel" if STORE_BYTES[st] == 2 and nx % 4 == 0 and nx <= 256
+              and (nx // 4) & (nx // 4 - 1) == 0 else "step_p1_rows_kernel")
+        return (f"step_p0_flat_kernel + {p1} (Q={q}, {st}), one launch per step alternating, "
+                "averaged over both")
+
+    def roofline(st, sh, kernel_ms):
+        ab = nfluid * 2 * q * STORE_BYTES[st] + (N if masked else 0)
+        achieved = ab / (kernel_ms * 1e-3) / 1e9
+        key = f"{args.workload}/{st}{'-shifted' if sh else ''}"
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(key, "lattice") if args.workload != "cavity" else None,
+                "algorithmic_bytes_per_launch": ab, "kernel": kernel_label(st)}
+
+    def timed_run(lt):
+        """init, warm up, then time exactly args.steps steps: (wall s, kernel ms/step, m0, m1)."""
+        lt.init_equilibrium(None, wl.u0)
+        m0 = lt.totals()[0]
+        lt.step(args.warmup)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        lt.step(args.steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, ev0.elapsed_time(ev1) / max(args.steps, 1), m0, lt.totals()[0]
 
     # --- oracle CPU baseline (rank 0, N=1), and a full-size parity sample ---
     cpu = None
@@ -477,27 +557,29 @@ def main():
         del src, dst
 
     # --- GPU timing ---
-    lat.init_equilibrium(None, wl.u0)
-    m0, _, _ = lat.totals()
-    lat.step(args.warmup)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    lat.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kernel_ms = ev0.elapsed_time(ev1) / max(args.steps, 1)
-    m1, j1, stats = lat.totals()
-
+    wall, kernel_ms, m0, m1 = timed_run(lat)
     ms_per_step = wall * 1e3 / max(args.steps, 1)
     mlups = N * args.steps / wall / 1e6
     mlups_fluid = nfluid * args.steps / wall / 1e6
-    sb = STORE_BYTES[storage]
-    alg_bytes = nfluid * 2 * q * sb + (N if masked else 0)
-    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+
+    # the other storages, timed the same way (FP16/BF16-stored vs FP32)
+    timed_variants = None
+    if args.variants:
+        timed_variants = {}
+        for v in args.variants.split(","):
+            st, sh = parse_variant(v.strip())
+            lt = make_lattice(st, sh)
+            w_v, k_v, mv0, mv1 = timed_run(lt)
+            lt.close()
+            del lt
+            torch.cuda.empty_cache()
+            timed_variants[v.strip()] = {
+                "value": round(N * args.steps / w_v / 1e6, 2), "unit": "MLUPS",
+                "ms_per_step": round(w_v * 1e3 / max(args.steps, 1), 5),
+                "kernel_ms_per_step": round(k_v, 5), "roofline": roofline(st, sh, k_v),
+                "mass_drift_rel": (mv1 - mv0) / mv0,
+                "speedup_vs_main": round(wall / w_v, 3),
+                "error_vs_oracle": (variants_err or {}).get(v.strip())}
 
     extra = {}
     if args.workload == "tgv3d":
@@ -531,13 +613,10 @@ def main():
                    "propagation": "AA in place"},
         "mlups_fluid": round(mlups_fluid, 2),
         "kernel_ms_per_step": round(kernel_ms, 5),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "kernel": f"step_kernel<Q={q},{storage}{',shifted' if shifted else ''}>"},
+        "roofline": roofline(storage, shifted, kernel_ms),
         "cpu_baseline": cpu,
         "oracle_parity": parity,
-        "storage_error_vs_oracle": variants_err,
+        "storage_variants": timed_variants,
         "storage_error_vs_f64_gpu": ref_err,
         "checks": extra,
         "paper_context": {"value": 17.2699, "unit": "MLUPs",

@@ -47,7 +47,7 @@ namespace {
 template <int Q, typename S, bool SHIFT, int PHASE, bool MASKED>
 __global__ void __launch_bounds__(256)
     step_kernel(S* __restrict__ pop, const uint32_t* __restrict__ link,
-                const uint32_t* __restrict__ mov, int nx, int ny, int nz, uint32_t N, int nxb,
+                const uint32_t* __restrict__ mov, int nx, int ny, int nz, uint32_t PS, int nxb,
                 StepParams<typename Store<S>::T> p) {
   using T = typename Store<S>::T;
   using V = Vel<Q>;
@@ -60,7 +60,6 @@ __global__ void __launch_bounds__(256)
   const uint32_t idx = (uint32_t)x + (uint32_t)nx * (uint32_t)(y + ny * z);
 
   const Nbr nb = make_nbr(x, y, z, nx, ny, nz);
-  const uint32_t PS = N;  // population stride
   uint32_t lw = LINK_FLUID, mv = 0;
   T f[Q];
   if (MASKED && PHASE == 1) {
@@ -71,15 +70,14 @@ __global__ void __launch_bounds__(256)
     lw = link[idx];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const S* a = pop + (size_t)V::opp[i] * PS;
-      const uint32_t k = nb.at(-V::cx[i], -V::cy[i], -V::cz[i]);
-      f[i] = V::cx[i] == 0 ? elem_load<S, true>(a, k) : elem_load<S, false>(a, k);
+      const uint32_t off = (uint32_t)V::opp[i] * PS + nb.at(-V::cx[i], -V::cy[i], -V::cz[i]);
+      f[i] = V::cx[i] == 0 ? load_nt<S>(pop + off) : Store<S>::load(pop + off);
     }
     if (!(lw & LINK_FLUID)) return;
     if (p.has_moving && (lw & LINK_HAS_MOVING)) mv = mov[idx];
 #pragma unroll
     for (int i = 1; i < Q; ++i)
-      if ((lw >> (V::opp[i] - 1)) & 1u) f[i] = elem_load<S, false>(pop + (size_t)i * PS, idx);
+      if ((lw >> (V::opp[i] - 1)) & 1u) f[i] = Store<S>::load(pop + (uint32_t)i * PS + idx);
   } else {
     if (MASKED) {
       lw = link[idx];
@@ -88,15 +86,18 @@ __global__ void __launch_bounds__(256)
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
+      uint32_t off;
+      if (PHASE == 0)
+        off = (uint32_t)i * PS + idx;
+      else
+        off = (uint32_t)V::opp[i] * PS + nb.at(-V::cx[i], -V::cy[i], -V::cz[i]);
       // Streaming data is touched once per launch: x-aligned accesses bypass
       // the caches; x-shifted ones (phase 1, c_x != 0) share lines with the
       // neighbouring wave and stay cached.
-      if (PHASE == 0)
-        f[i] = elem_load<S, true>(pop + (size_t)i * PS, idx);
-      else if (V::cx[i] == 0)
-        f[i] = elem_load<S, true>(pop + (size_t)V::opp[i] * PS, nb.at(0, -V::cy[i], -V::cz[i]));
+      if (PHASE == 0 || V::cx[i] == 0)
+        f[i] = load_nt<S>(pop + off);
       else
-        f[i] = elem_load<S, false>(pop + (size_t)V::opp[i] * PS, nb.at(-V::cx[i], -V::cy[i], -V::cz[i]));
+        f[i] = Store<S>::load(pop + off);
     }
   }
 
@@ -106,15 +107,17 @@ __global__ void __launch_bounds__(256)
   for (int i = 0; i < Q; ++i) {
     T v = f[i];
     if (MASKED && i > 0 && ((mv >> (i - 1)) & 1u)) v -= rho * p.mw[i];
+    uint32_t off;
     if (PHASE == 0) {
-      elem_store<S, true>(pop + (size_t)V::opp[i] * PS, idx, v);
-    } else if (MASKED && i > 0 && ((lw >> (i - 1)) & 1u)) {
-      elem_store<S, false>(pop + (size_t)V::opp[i] * PS, idx, v);
-    } else if (V::cx[i] == 0) {
-      elem_store<S, true>(pop + (size_t)i * PS, nb.at(0, V::cy[i], V::cz[i]), v);
+      off = (uint32_t)V::opp[i] * PS + idx;
     } else {
-      elem_store<S, false>(pop + (size_t)i * PS, nb.at(V::cx[i], V::cy[i], V::cz[i]), v);
+      off = (uint32_t)i * PS + nb.at(V::cx[i], V::cy[i], V::cz[i]);
+      if (MASKED && i > 0 && ((lw >> (i - 1)) & 1u)) off = (uint32_t)V::opp[i] * PS + idx;
     }
+    if (PHASE == 0 || V::cx[i] == 0)
+      store_nt<S>(pop + off, v);
+    else
+      Store<S>::store(pop + off, v);
   }
 }
 

@@ -46,12 +46,17 @@ CASES_3D = [
     ((70, 9, 7), 0b011),   # more than one x-block of 64 threads, ragged tail
     ((300, 4, 3), 0b111),  # two 256-wide x-blocks, ragged tail
     ((64, 34, 32), 0b001),  # >= 65536 cells: masked lattices take the flat phase-0 kernel
+    # >= 65536 cells, rows that split unevenly: per storage, the masked row
+    # kernel (phase 1) or the per-cell kernel, one or several rows per block
+    ((66, 33, 31), 0b011),
+    ((520, 12, 11), 0b111),
 ]
 CASES_2D = [
     ((9, 7, 1), 0b00),
     ((12, 10, 1), 0b01),
     ((8, 9, 1), 0b11),
     ((130, 5, 1), 0b01),
+    ((272, 256, 1), 0b01),  # >= 65536 cells, masked row kernel with 1..3 rows per block
 ]
 # Fully fluid periodic boxes take the row/flat fast path when nx is a multiple
 # of the cells per lane (8 bytes / storage size) and a row fits 256 lanes;
@@ -227,7 +232,8 @@ def test_fp64_full_steps_fluid_box(orc, lbm, shifted, d, shape):
 @pytest.mark.parametrize("storage,shifted", [("f64", True), ("f32", False), ("f32", True),
                                              ("f16", True), ("bf16", True)])
 @pytest.mark.parametrize("d,case", [(1, CASES_3D[0]), (1, CASES_3D[3]), (1, CASES_3D[4]),
-                                    (1, CASES_3D[6]), (0, CASES_2D[0]), (0, CASES_2D[3]),
+                                    (1, CASES_3D[6]), (1, CASES_3D[7]), (1, CASES_3D[8]),
+                                    (0, CASES_2D[0]), (0, CASES_2D[3]), (0, CASES_2D[4]),
                                     (1, ((64, 4, 3), "fluid")), (1, ((12, 5, 4), "fluid")),
                                     (0, ((128, 6, 1), "fluid"))])
 @pytest.mark.parametrize("parity", [0, 1])
@@ -277,7 +283,8 @@ def test_one_step_within_storage_ulp(orc, lbm, storage, shifted, d, case, parity
 # FP32: many steps
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("shifted", [False, True])
-@pytest.mark.parametrize("d,case", [(1, CASES_3D[2]), (1, CASES_3D[4]), (0, CASES_2D[2]),
+@pytest.mark.parametrize("d,case", [(1, CASES_3D[2]), (1, CASES_3D[4]), (1, CASES_3D[7]),
+                                    (0, CASES_2D[2]), (0, CASES_2D[4]),
                                     (1, ((64, 6, 5), "fluid")), (0, ((128, 16, 1), "fluid"))])
 def test_fp32_many_steps(orc, lbm, shifted, d, case):
     shape, periodic = case
