@@ -39,6 +39,40 @@ using namespace lbm;
 
 namespace {
 
+// A stored population held in a full register (16-bit values zero-extended),
+// so that a conditional reload overwrites a whole register.
+template <typename S>
+struct RawReg {
+  using type = uint32_t;
+  static __device__ __forceinline__ type load(const S* p) {
+    if constexpr (sizeof(S) == 2) return *(const uint16_t*)p;
+    else return *(const uint32_t*)p;
+  }
+  static __device__ __forceinline__ type load_nt(const S* p) {
+    if constexpr (sizeof(S) == 2) return __builtin_nontemporal_load((const uint16_t*)p);
+    else return __builtin_nontemporal_load((const uint32_t*)p);
+  }
+  static __device__ __forceinline__ typename Store<S>::T cvt(type r) {
+    S v;
+    if constexpr (sizeof(S) == 2) {
+      const uint16_t h = (uint16_t)r;
+      __builtin_memcpy(&v, &h, 2);
+    } else {
+      __builtin_memcpy(&v, &r, 4);
+    }
+    return Store<S>::cvt(v);
+  }
+};
+template <>
+struct RawReg<double> {
+  using type = double;
+  static __device__ __forceinline__ double load(const double* p) { return *p; }
+  static __device__ __forceinline__ double load_nt(const double* p) {
+    return __builtin_nontemporal_load(p);
+  }
+  static __device__ __forceinline__ double cvt(double r) { return r; }
+};
+
 // ---------------------------------------------------------------------------
 // The fused step kernel.  One thread per cell; a block covers a run of up to
 // blockDim.x cells along x of one (y, z) row.
@@ -67,17 +101,24 @@ __global__ void __launch_bounds__(256)
     // one memory latency per wave); a wall cell's lanes read values nobody
     // uses, and the populations reflected by a wall are then re-read from the
     // cell's own slots.
+    // The stored values are kept raw, one full register each, until every
+    // load is in flight: a 16-bit value converted inside the wall branch
+    // would make each branch wait for its own load.
+    using U = typename RawReg<S>::type;
+    U raw[Q];
     lw = link[idx];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const uint32_t off = (uint32_t)V::opp[i] * PS + nb.at(-V::cx[i], -V::cy[i], -V::cz[i]);
-      f[i] = V::cx[i] == 0 ? load_nt<S>(pop + off) : Store<S>::load(pop + off);
+      raw[i] = V::cx[i] == 0 ? RawReg<S>::load_nt(pop + off) : RawReg<S>::load(pop + off);
     }
     if (!(lw & LINK_FLUID)) return;
     if (p.has_moving && (lw & LINK_HAS_MOVING)) mv = mov[idx];
 #pragma unroll
     for (int i = 1; i < Q; ++i)
-      if ((lw >> (V::opp[i] - 1)) & 1u) f[i] = Store<S>::load(pop + (uint32_t)i * PS + idx);
+      if ((lw >> (V::opp[i] - 1)) & 1u) raw[i] = RawReg<S>::load(pop + (uint32_t)i * PS + idx);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = RawReg<S>::cvt(raw[i]);
   } else {
     if (MASKED) {
       lw = link[idx];
