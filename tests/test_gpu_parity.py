@@ -315,7 +315,10 @@ def test_fp32_many_steps(orc, lbm, shifted, d, case):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("d,shape,periodic,storage", [(1, (20, 12, 10), 0b001, "f32"),
                                                       (1, (64, 8, 6), 0b111, "f16"),
-                                                      (0, (64, 64, 1), 0b00, "f64")])
+                                                      (0, (64, 64, 1), 0b00, "f64"),
+                                                      (1, (40, 24, 20), 0b001, "f32"),
+                                                      (1, (64, 16, 20), 0b111, "f16"),
+                                                      (0, (160, 128, 1), 0b00, "f64")])
 def test_graph_replay_matches_direct_launches(orc, lbm, d, shape, periodic, storage):
     """Replays of a captured 10-step graph, interleaved with eager work and
     synchronisation, give bit-identical states to direct launches every time."""
