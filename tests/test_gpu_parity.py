@@ -60,9 +60,11 @@ CASES_2D = [
 ]
 # Fully fluid periodic boxes take the row/flat fast path when nx is a multiple
 # of the cells per lane (8 bytes / storage size) and a row fits 256 lanes;
-# the shapes cover one and many rows per block, 2..256 lanes per row, and
-# shapes that fall back to the per-cell kernel (nx not a multiple).
-FLUID_3D = [(8, 6, 5), (12, 5, 4), (64, 4, 3), (256, 3, 2), (512, 2, 3), (6, 5, 4), (20, 3, 7)]
+# the shapes cover rows held by part of a wave or one wave (16-bit storage),
+# the LDS row tile with one and many rows per block, and shapes that fall
+# back to the per-cell kernel (nx not a multiple).
+FLUID_3D = [(8, 6, 5), (12, 5, 4), (64, 4, 3), (256, 3, 2), (512, 2, 3), (6, 5, 4), (20, 3, 7),
+            (256, 5, 3), (512, 3, 3)]  # a last LDS-row block half used
 FLUID_2D = [(16, 10, 1), (128, 6, 1), (36, 7, 1), (10, 9, 1)]
 
 
