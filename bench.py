@@ -152,7 +152,16 @@ def cpu_baseline(wl, budget_s, u0, fixed_steps=0):
         elif el >= budget_s or steps >= 1000:
             break
     cores = oracle.num_threads()
-    return ref, steps, el, nfluid, cores
+    # the same oracle on one core, one step (the guide's reference runs are
+    # single-process CPU runs)
+    one = oracle.Lattice(wl.descriptor, wl.material, wl.periodic, wl.tau, g=wl.g,
+                         u_wall=wl.u_wall, nthreads=1)
+    one.init_equilibrium(None, None if u0 is None else u0[: (3 if wl.descriptor else 2)])
+    t1 = time.perf_counter()
+    one.step(1)
+    single = time.perf_counter() - t1
+    del one
+    return ref, steps, el, nfluid, cores, single
 
 
 def bench_ensemble(args):
@@ -486,12 +495,14 @@ def main():
     parity = None
     variants_err = None
     if not args.no_cpu_baseline:
-        ref, csteps, cel, cfluid, cores = cpu_baseline(wl, args.cpu_seconds, wl.u0,
-                                                       args.oracle_steps)
+        ref, csteps, cel, cfluid, cores, single = cpu_baseline(wl, args.cpu_seconds, wl.u0,
+                                                               args.oracle_steps)
         cpu = {"value": round(N * csteps / cel / 1e6, 3), "unit": "MLUPS", "cores": cores,
                "kind": "oracle",
                "sample": f"{csteps} steps of the full {nx}x{ny}x{nz} lattice (FP64 oracle, "
-                         f"{cel:.1f} s wall, OpenMP over z-planes)"}
+                         f"{cel:.1f} s wall, OpenMP over z-planes)",
+               "single_core": {"value": round(N / single / 1e6, 3), "unit": "MLUPS",
+                               "sample": f"1 step of the same lattice on 1 thread, {single:.1f} s"}}
         rho_o, u_o = ref.moments()
         fl = wl.material == 1
 

@@ -302,7 +302,8 @@ int orc_step(int d, int nx, int ny, int nz, const uint8_t *mat,
   const long N = (long)nx * ny * nz;
   const int q = D.q;
 #ifdef _OPENMP
-  if (nthreads > 0) omp_set_num_threads(nthreads);
+  /* the thread count applies to this call only */
+  const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #else
   (void)nthreads;
 #endif
@@ -313,7 +314,7 @@ int orc_step(int d, int nx, int ny, int nz, const uint8_t *mat,
 
   /* Each destination slot of B is written by exactly one fluid cell, so
    * z-planes can be processed independently. */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) num_threads(nt)
   for (int z = 0; z < nz; ++z) {
     for (int y = 0; y < ny; ++y) {
       for (int x = 0; x < nx; ++x) {
@@ -468,7 +469,8 @@ int orc_porous_step(int d, int nx, int ny, int nz, const uint8_t *mat, unsigned 
   const long N = (long)nx * ny * nz;
   const int q = D.q;
 #ifdef _OPENMP
-  if (nthreads > 0) omp_set_num_threads(nthreads);
+  /* the thread count applies to this call only */
+  const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #else
   (void)nthreads;
 #endif
@@ -477,7 +479,7 @@ int orc_porous_step(int d, int nx, int ny, int nz, const uint8_t *mat, unsigned 
     if (mat[idx] != MAT_FLUID)
       for (int i = 0; i < q; ++i) B[i * N + idx] = A[i * N + idx];
   }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) num_threads(nt)
   for (int z = 0; z < nz; ++z)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
@@ -586,7 +588,7 @@ int orc_porous_gradient(int d, int nx, int ny, int nz, const uint8_t *mat, unsig
 
   for (int t = nsteps - 1; t >= 0; --t) {
     const double *ft = hist + state * (size_t)t;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
     for (int z = 0; z < nz; ++z)
       for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {

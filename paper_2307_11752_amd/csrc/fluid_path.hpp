@@ -19,7 +19,6 @@
 namespace lbm {
 
 typedef uint32_t raw8 __attribute__((ext_vector_type(2)));
-typedef uint32_t raw16 __attribute__((ext_vector_type(4)));
 
 template <int BYTES>
 struct RawOf;
@@ -34,10 +33,6 @@ struct RawOf<4> {
 template <>
 struct RawOf<8> {
   using type = raw8;
-};
-template <>
-struct RawOf<16> {
-  using type = raw16;
 };
 
 // C consecutive values of storage type S as one machine word.
@@ -71,30 +66,6 @@ __device__ __forceinline__ global_ptr<R> at_byte(const S* base, uint32_t byte_of
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
   return (global_ptr<R>)((__attribute__((address_space(1))) char*)(((uint64_t)hi << 32) | lo) + byte_off);
-}
-
-// One population value at element idx of the array at (uniform) base, in the
-// compute type; NT selects a non-temporal access.
-template <typename S, bool NT>
-__device__ __forceinline__ typename Store<S>::T elem_load(const S* base, uint32_t idx) {
-  using U = typename RawOf<(int)sizeof(S)>::type;
-  const global_ptr<U> q = at_byte<U>(base, idx * (uint32_t)sizeof(S));
-  const U u = NT ? __builtin_nontemporal_load(q) : *q;
-  S v;
-  __builtin_memcpy(&v, &u, sizeof(S));
-  return Store<S>::cvt(v);
-}
-template <typename S, bool NT>
-__device__ __forceinline__ void elem_store(S* base, uint32_t idx, typename Store<S>::T v) {
-  using U = typename RawOf<(int)sizeof(S)>::type;
-  const S s = Store<S>::pack(v);
-  U u;
-  __builtin_memcpy(&u, &s, sizeof(S));
-  const global_ptr<U> q = at_byte<U>(base, idx * (uint32_t)sizeof(S));
-  if (NT)
-    __builtin_nontemporal_store(u, q);
-  else
-    *q = u;
 }
 
 template <int Q>
