@@ -56,7 +56,8 @@ typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 } lbm_descriptor;
 typedef enum {
   LBM_STORE_F64 = 0,
   LBM_STORE_F32 = 1,
-  LBM_STORE_F16 = 2,  /* IEEE binary16 */
+  LBM_STORE_F16 = 2,  /* IEEE binary16 holding the value times 2^12 (so that small
+                         weight-shifted values stay normal); |value| < 16 */
   LBM_STORE_BF16 = 3  /* bfloat16 */
 } lbm_storage;
 

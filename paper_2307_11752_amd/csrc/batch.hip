@@ -60,6 +60,7 @@ __global__ void __launch_bounds__(512)
     const BatchItem item = items[it];
     const BatchItem& L = item;
     StepParams<T> p{};
+    p.base = (T)Store<S>::unit;
     p.omega = (T)L.omega;
     p.kguo = (T)(1.0 - 0.5 * L.omega);
     S* pop = base + L.pop_off;

@@ -62,6 +62,7 @@ struct Store;
 template <>
 struct Store<double> {
   using T = double;
+  static constexpr double unit = 1.0;
   static __device__ __forceinline__ T load(const double* p) { return *p; }
   static __device__ __forceinline__ void store(double* p, T v) { *p = v; }
   static __device__ __forceinline__ double to_f64(double v) { return v; }
@@ -73,6 +74,7 @@ struct Store<double> {
 template <>
 struct Store<float> {
   using T = float;
+  static constexpr float unit = 1.0f;
   static __device__ __forceinline__ T load(const float* p) { return *p; }
   static __device__ __forceinline__ void store(float* p, T v) { *p = v; }
   static __device__ __forceinline__ double to_f64(float v) { return (double)v; }
@@ -81,13 +83,29 @@ struct Store<float> {
   static __device__ __forceinline__ float pack(T v) { return v; }
 };
 
+// FP16 storage holds the value times 2^12 (an exact power-of-two scale).  The
+// weight-shifted populations of a slow flow, |f - w| down to ~1e-7, then sit
+// in binary16's normal range (from 6.1e-5 / 2^12 = 1.5e-8) instead of among
+// its subnormals, whose fixed spacing of 6e-8 would otherwise be the rounding
+// error; any |value| < 16 still fits.  The step kernels work on the scaled
+// values directly: the collision is homogeneous of degree one in (f, base)
+// (StepParams::base, the density of the shifted rest state), so they only
+// set base = 2^12 and convert without any multiply; the decoding and encoding
+// routines (to_f64, from_f64) apply the scale.
+constexpr float F16_SCALE = 4096.0f;
+
 template <>
 struct Store<_Float16> {
   using T = float;
+  static constexpr float unit = F16_SCALE;  // stored value of 1.0
   static __device__ __forceinline__ T load(const _Float16* p) { return (float)*p; }
   static __device__ __forceinline__ void store(_Float16* p, T v) { *p = (_Float16)v; }
-  static __device__ __forceinline__ double to_f64(_Float16 v) { return (double)(float)v; }
-  static __device__ __forceinline__ _Float16 from_f64(double v) { return (_Float16)v; }
+  static __device__ __forceinline__ double to_f64(_Float16 v) {
+    return (double)(float)v / (double)F16_SCALE;
+  }
+  static __device__ __forceinline__ _Float16 from_f64(double v) {
+    return (_Float16)(v * (double)F16_SCALE);
+  }
   static __device__ __forceinline__ T cvt(_Float16 v) { return (float)v; }
   static __device__ __forceinline__ _Float16 pack(T v) { return (_Float16)v; }
 };
@@ -101,6 +119,7 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float v) {
 template <>
 struct Store<bf16s> {
   using T = float;
+  static constexpr float unit = 1.0f;
   static __device__ __forceinline__ T load(const bf16s* p) {
     return __uint_as_float((uint32_t)p->bits << 16);
   }
@@ -152,6 +171,7 @@ constexpr uint32_t LINK_HAS_MOVING = 1u << 30;
 
 template <typename T>
 struct StepParams {
+  T base;       // stored value of 1.0 (Store<S>::unit): the rest density of shifted storage
   T omega;      // 1/tau
   T kguo;       // 1 - omega/2
   T g[3];       // body acceleration
@@ -161,7 +181,8 @@ struct StepParams {
 };
 
 // One BGK + Guo collision of a cell held in registers (in place).
-//   rho = base + sum f  (base = 1 when f stores f_i - w_i, else 0)
+//   rho = base + sum f  (base = p.base when f stores f_i - w_i, else 0;
+//                        p.base = 1 unless the storage holds scaled values)
 //   u   = j/rho + g/2                                  (Guo velocity shift)
 //   feq_i - base*w_i = w_i (sum f + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u))
 //   f*_i = f_i + omega (feq_i - f_i) + (1 - omega/2) w_i (3 (c_i - u).F + 9 (c_i.u)(c_i.F))
@@ -180,7 +201,7 @@ __device__ __forceinline__ T collide(T (&f)[Q], const StepParams<T>& p) {
     if (V::cz[i] > 0) jz += f[i];
     if (V::cz[i] < 0) jz -= f[i];
   }
-  const T rho = SHIFT ? T(1) + sf : sf;
+  const T rho = SHIFT ? p.base + sf : sf;
   const T inv = T(1) / rho;
   T ux = jx * inv, uy = jy * inv, uz = jz * inv;
   if (p.has_force) {

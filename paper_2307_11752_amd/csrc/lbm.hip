@@ -686,7 +686,8 @@ struct Ops {
   }
 
   static void step(lbm_lattice* h, int phase) {
-    const StepParams<T> p = make_params<T>(h);
+    StepParams<T> p = make_params<T>(h);
+    p.base = (T)Store<S>::unit;
     S* pop = (S*)h->pop;
     const uint32_t* link = (const uint32_t*)(h->aux + h->lay.link);
     const uint32_t* mov = (const uint32_t*)(h->aux + h->lay.mov);

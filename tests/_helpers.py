@@ -7,6 +7,8 @@ import numpy as np
 
 STORAGES = ("f64", "f32", "f16", "bf16")
 EPS_COMPUTE = {"f64": 2.0**-53, "f32": 2.0**-24, "f16": 2.0**-24, "bf16": 2.0**-24}
+# the library's FP16 storage holds the value times 2^12 (include/lbm.h)
+F16_SCALE = 4096.0
 
 
 def _bf16_round(a):
@@ -25,7 +27,7 @@ def round_storage(a, storage):
     if storage == "f32":
         return a.astype(np.float32).astype(np.float64)
     if storage == "f16":
-        return a.astype(np.float16).astype(np.float64)
+        return (a * F16_SCALE).astype(np.float16).astype(np.float64) / F16_SCALE
     if storage == "bf16":
         return _bf16_round(a)
     raise ValueError(storage)
@@ -34,10 +36,11 @@ def round_storage(a, storage):
 def ulp_storage(a, storage):
     """Spacing of the storage type at |a| (normal range; subnormal spacing below)."""
     a = np.abs(np.asarray(a, dtype=np.float64))
+    scale = F16_SCALE if storage == "f16" else 1.0
     bits = {"f64": 52, "f32": 23, "f16": 10, "bf16": 7}[storage]
     tiny = {"f64": 2.0**-1022, "f32": 2.0**-126, "f16": 2.0**-14, "bf16": 2.0**-126}[storage]
-    e = np.floor(np.log2(np.maximum(a, tiny)))
-    return 2.0 ** (e - bits)
+    e = np.floor(np.log2(np.maximum(a * scale, tiny)))
+    return 2.0 ** (e - bits) / scale
 
 
 def encode_decode(f, w, storage, shifted):
