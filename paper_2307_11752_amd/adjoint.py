@@ -15,6 +15,7 @@ import numpy as np
 import torch
 
 from ._lib import check_porous, load
+from .lattice import stream_order
 
 
 def _vec3(v):
@@ -57,23 +58,23 @@ class PorousChannel:
 
     def forward(self, porosity):
         """J for a float32 device tensor of shape (nz, ny, nx)."""
-        with torch.cuda.stream(self.stream):
-            d = porosity.detach().to(device=self.device, dtype=torch.float32).contiguous()
-            J = ctypes.c_double()
+        d = porosity.detach().to(device=self.device, dtype=torch.float32).contiguous()
+        J = ctypes.c_double()
+        with stream_order(self.stream, self.device):
             self._chk(self.lib.lbm_porous_forward(self.h, ctypes.c_void_p(d.data_ptr()),
                                                   ctypes.byref(J)))
         return J.value
 
     def backward(self):
         """dJ/dd of the last forward run, float32 tensor (nz, ny, nx)."""
-        with torch.cuda.stream(self.stream):
-            grad = torch.empty(self.shape_zyx, dtype=torch.float32, device=self.device)
+        grad = torch.empty(self.shape_zyx, dtype=torch.float32, device=self.device)
+        with stream_order(self.stream, self.device):
             self._chk(self.lib.lbm_porous_backward(self.h, ctypes.c_void_p(grad.data_ptr())))
         return grad
 
     def final_populations(self):
-        with torch.cuda.stream(self.stream):
-            f = torch.empty((19,) + tuple(self.shape_zyx), dtype=torch.float64, device=self.device)
+        f = torch.empty((19,) + tuple(self.shape_zyx), dtype=torch.float64, device=self.device)
+        with stream_order(self.stream, self.device):
             self._chk(self.lib.lbm_porous_get_final(self.h, ctypes.c_void_p(f.data_ptr())))
         return f
 

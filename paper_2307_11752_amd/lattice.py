@@ -6,6 +6,7 @@ the gfx950 kernels of liblbm_hip.so.  Names follow the C calls: ``step(n)`` is
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 
 import numpy as np
@@ -36,6 +37,28 @@ def validate_geometry(descriptor, material, periodic):
     nz, ny, nx = mat.shape
     return lib.lbm_validate_geometry(descriptor, nx, ny, nz,
                                      mat.ctypes.data_as(ctypes.c_void_p), int(periodic))
+
+
+@contextlib.contextmanager
+def stream_order(stream, device):
+    """Order a library call on a handle's stream between the caller's work.
+
+    The library launches on the stream its handle was created with.  Work the
+    caller queued on its current stream before the call (producing an input,
+    staging copies, allocating an output) completes before the call's kernels
+    start, and the caller's later work waits for them.  Inputs are staged and
+    outputs allocated on the caller's stream, so the caching allocator keeps
+    their memory ordered on that stream alone.
+    """
+    caller = torch.cuda.current_stream(device)
+    same = caller.cuda_stream == stream.cuda_stream
+    if not same:
+        stream.wait_stream(caller)
+    try:
+        yield
+    finally:
+        if not same:
+            caller.wait_stream(stream)
 
 
 def _vec3(v):
@@ -127,28 +150,28 @@ class Lattice(_Handle):
             raise ValueError(f"expected {n} values, got {t.numel()}")
         return t
 
-    # All torch work of a call (staging copies, output allocation) is ordered on
-    # the lattice's stream, the stream the library launches on.
+    # Inputs are staged and outputs allocated on the caller's stream; each call
+    # is ordered after that work and before the caller's next (stream_order).
     def init_equilibrium(self, rho=None, u=None):
         """rho: N values or None (1); u: (dim or 3, N...) values or None (0)."""
-        with torch.cuda.stream(self.stream):
-            r = self._dev64(rho, self.N)
-            uu = None
-            if u is not None:
-                ut = torch.as_tensor(u, dtype=torch.float64).reshape(-1, self.N)
-                full = torch.zeros((3, self.N), dtype=torch.float64)
-                full[: ut.shape[0]] = ut.cpu() if ut.device.type != "cpu" else ut
-                uu = full.to(self.device)
+        r = self._dev64(rho, self.N)
+        uu = None
+        if u is not None:
+            ut = torch.as_tensor(u, dtype=torch.float64).reshape(-1, self.N)
+            full = torch.zeros((3, self.N), dtype=torch.float64)
+            full[: ut.shape[0]] = ut.cpu() if ut.device.type != "cpu" else ut
+            uu = full.to(self.device)
+        with stream_order(self.stream, self.device):
             self._chk(self.lib.lbm_init_equilibrium(
                 self.h, None if r is None else ctypes.c_void_p(r.data_ptr()),
                 None if uu is None else ctypes.c_void_p(uu.data_ptr())))
-            self.stream.synchronize()
+        self.stream.synchronize()
 
     def set_populations(self, f):
-        with torch.cuda.stream(self.stream):
-            t = self._dev64(f, self.q * self.N)
+        t = self._dev64(f, self.q * self.N)
+        with stream_order(self.stream, self.device):
             self._chk(self.lib.lbm_set_populations(self.h, ctypes.c_void_p(t.data_ptr())))
-            self.stream.synchronize()
+        self.stream.synchronize()
 
     # -- hot path -----------------------------------------------------------
     def step(self, n=1):
@@ -161,23 +184,21 @@ class Lattice(_Handle):
     # -- read-back ----------------------------------------------------------
     def get_populations(self):
         """Populations in natural layout, float64 tensor (q, nz, ny, nx) on the GPU."""
-        with torch.cuda.stream(self.stream):
-            out = torch.empty((self.q, self.nz, self.ny, self.nx), dtype=torch.float64,
-                              device=self.device)
+        out = torch.empty((self.q, self.nz, self.ny, self.nx), dtype=torch.float64,
+                          device=self.device)
+        with stream_order(self.stream, self.device):
             self._chk(self.lib.lbm_get_populations(self.h, ctypes.c_void_p(out.data_ptr())))
-            self.stream.synchronize()
+        self.stream.synchronize()
         return out
 
     def moments(self):
         """(rho (nz,ny,nx), u (3,nz,ny,nx)) float64 tensors on the GPU."""
-        with torch.cuda.stream(self.stream):
-            rho = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64,
-                              device=self.device)
-            u = torch.empty((3, self.nz, self.ny, self.nx), dtype=torch.float64,
-                            device=self.device)
+        rho = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        u = torch.empty((3, self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        with stream_order(self.stream, self.device):
             self._chk(self.lib.lbm_moments(self.h, ctypes.c_void_p(rho.data_ptr()),
                                            ctypes.c_void_p(u.data_ptr())))
-            self.stream.synchronize()
+        self.stream.synchronize()
         return rho, u
 
     def totals(self):

@@ -46,8 +46,8 @@ CASES_3D = [
     ((70, 9, 7), 0b011),   # more than one x-block of 64 threads, ragged tail
     ((300, 4, 3), 0b111),  # two 256-wide x-blocks, ragged tail
     ((64, 34, 32), 0b001),  # >= 65536 cells: masked lattices take the flat phase-0 kernel
-    # >= 65536 cells, rows that split unevenly: per storage, the masked row
-    # kernel (phase 1) or the per-cell kernel, one or several rows per block
+    # >= 65536 cells, rows not a multiple of 64: flat phase 0 with a ragged tail,
+    # per-cell phase 1
     ((66, 33, 31), 0b011),
     ((520, 12, 11), 0b111),
 ]
@@ -56,7 +56,7 @@ CASES_2D = [
     ((12, 10, 1), 0b01),
     ((8, 9, 1), 0b11),
     ((130, 5, 1), 0b01),
-    ((272, 256, 1), 0b01),  # >= 65536 cells, masked row kernel with 1..3 rows per block
+    ((272, 256, 1), 0b01),  # >= 65536 cells: masked D2Q9 takes the flat phase-0 kernel
 ]
 # Fully fluid periodic boxes take the row/flat fast path when nx is a multiple
 # of the cells per lane (8 bytes / storage size) and a row fits 256 lanes;
@@ -357,6 +357,32 @@ def test_graph_replay_matches_direct_launches(orc, lbm, d, shape, periodic, stor
         lat.step(20)
     assert torch.equal(a.get_populations(), b.get_populations())
     assert a.info()[0] == b.info()[0] == 101
+
+
+# ---------------------------------------------------------------------------
+# Stream order between the caller's stream and the lattice's stream
+# ---------------------------------------------------------------------------
+def test_inputs_from_a_busy_caller_stream(lbm):
+    """A lattice on a stream of its own reads an input that the caller's stream
+    is still producing (queued behind ~40 GB of unrelated traffic): the library
+    call waits for it, and the output is ordered before the caller's next work."""
+    shape = (40, 24, 20)
+    nx, ny, nz = shape
+    s = torch.cuda.Stream()
+    lat = lbm.Lattice(1, shape, 0.8, storage="f32", stream=s)
+    lat.set_geometry(np.ones((nz, ny, nx), np.uint8), 7)
+    rng = np.random.default_rng(5)
+    want = torch.from_numpy(rng.integers(1, 1024, size=(19, nz, ny, nx)) / 1024.0).cuda()
+    torch.cuda.synchronize()
+    busy = torch.ones(2**28, device="cuda")
+    f = torch.zeros_like(want)
+    for _ in range(20):
+        busy.mul_(1.0)
+    f.copy_(want)
+    lat.set_populations(f)  # f32 holds k / 1024 exactly
+    got = lat.get_populations()
+    assert torch.equal(got, want)
+    lat.close()
 
 
 # ---------------------------------------------------------------------------
