@@ -75,12 +75,17 @@ typedef enum {
 } lbm_status;
 
 /* Sizes of the two caller-allocated device buffers for a lattice.
- * pop_bytes: q population arrays of the storage type (structure of arrays:
- * population i of cell idx at element i*PS + idx, where the stride PS is N
- * rounded up to a multiple of 64 so every array starts on a 256-byte
- * boundary; the value stored depends on the propagation phase, so read
- * populations with lbm_get_populations).  aux_bytes: per-cell link masks
- * plus reduction scratch.  Host-only; needs no GPU. */
+ * pop_bytes: the populations in the storage type.  With s bytes per value and
+ * B = 32768 / s cells per chunk, a lattice of more than B cells whose buffer
+ * stays below 2^32 bytes is blocked: N is rounded up to whole chunks, and
+ * population i of cell idx sits at element
+ *   (idx / B) * q * B + i * B + idx % B
+ * (each chunk holds its q runs of B values back to back).  Otherwise the
+ * buffer holds one array per population: element i * PS + idx, with PS = N
+ * rounded up to a multiple of 64.  The value stored depends on the
+ * propagation phase, so read populations with lbm_get_populations.
+ * aux_bytes: per-cell link masks plus reduction scratch.  Host-only; needs no
+ * GPU. */
 lbm_status lbm_required_bytes(lbm_descriptor d, int nx, int ny, int nz, lbm_storage s,
                               size_t* pop_bytes, size_t* aux_bytes);
 

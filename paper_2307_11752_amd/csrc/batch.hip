@@ -29,7 +29,8 @@ namespace {
 struct BatchLat {
   uint64_t pop_off;  // element offset of the lattice's populations in the batch buffer
   int nx, ny, nz;
-  uint32_t N, PS;  // cells, population stride
+  uint32_t N;  // cells
+  PopIndex pix;  // placement of the lattice's populations
   double omega;
   int c;    // cells per lane: 8 bytes' worth when nx allows it, else 1
   int tpr;  // lanes per x-row = nx / c
@@ -40,7 +41,8 @@ struct BatchLat {
 struct BatchItem {
   uint64_t pop_off;
   double omega;
-  uint32_t N, PS;
+  uint32_t N;
+  PopIndex pix;
   int nx, ny, nz;
   int c, tpr;
   uint32_t first;  // phase 0: first cell; phase 1: first x-row
@@ -68,9 +70,9 @@ __global__ void __launch_bounds__(512)
       const uint32_t c0 = item.first + (uint32_t)L.c * threadIdx.x;
       if (c0 < item.first + item.count) {
         if (L.c == CM)
-          fluid_cells_p0<Q, S, SHIFT, CM>(pop, L.PS, c0, p);
+          fluid_cells_p0<Q, S, SHIFT, CM>(pop, L.pix, c0, p);
         else
-          fluid_cells_p0<Q, S, SHIFT, 1>(pop, L.PS, c0, p);
+          fluid_cells_p0<Q, S, SHIFT, 1>(pop, L.pix, c0, p);
       }
     } else {
       const int rloc = (int)threadIdx.x / L.tpr;
@@ -79,9 +81,9 @@ __global__ void __launch_bounds__(512)
       const int row = (int)item.first + rloc;
       S* tile = (S*)smem_raw + (size_t)rloc * Shifted<Q>::count() * L.nx;
       if (L.c == CM)
-        fluid_rows_p1<Q, S, SHIFT, CM>(pop, L.nx, L.ny, L.nz, L.PS, row, active, t, tile, p);
+        fluid_rows_p1<Q, S, SHIFT, CM>(pop, L.nx, L.ny, L.nz, L.pix, row, active, t, tile, p);
       else
-        fluid_rows_p1<Q, S, SHIFT, 1>(pop, L.nx, L.ny, L.nz, L.PS, row, active, t, tile, p);
+        fluid_rows_p1<Q, S, SHIFT, 1>(pop, L.nx, L.ny, L.nz, L.pix, row, active, t, tile, p);
       __syncthreads();  // the next item reuses the LDS tile
     }
   }
@@ -226,7 +228,7 @@ lbm_status build_items(lbm_batch* b, int threads) {
   i1.reserve(b->lay.max_items1);
   for (int l = 0; l < b->count; ++l) {
     const BatchLat& L = b->lats[l];
-    BatchItem it{L.pop_off, L.omega, L.N, L.PS, L.nx, L.ny, L.nz, L.c, L.tpr, 0, 0};
+    BatchItem it{L.pop_off, L.omega, L.N, L.pix, L.nx, L.ny, L.nz, L.c, L.tpr, 0, 0};
     const uint32_t chunk = (uint32_t)threads * (uint32_t)L.c;
     for (uint32_t c = 0; c < L.N; c += chunk) {
       it.first = c;
@@ -364,7 +366,7 @@ lbm_status lbm_batch_create(lbm_batch** out, lbm_descriptor d, int count, const 
     bl.ny = ny;
     bl.nz = nz;
     bl.N = (uint32_t)v->N;
-    bl.PS = (uint32_t)v->ps;
+    bl.pix = v->pix;
     bl.omega = v->omega;
     const int cmax = 8 / (int)storage_bytes(s);
     bl.c = nx % cmax == 0 ? cmax : 1;

@@ -2,7 +2,8 @@
 // the single-lattice kernels (lbm.hip) and the batched ensemble (batch.hip).
 //
 // Every lane moves C consecutive cells of one population (C * sizeof(S) bytes,
-// at most 8) with one aligned, non-temporal access per direction.
+// at most 8) with one aligned, non-temporal access per direction; PopIndex
+// places the populations in the buffer.
 //   phase 0 needs no neighbour: flat cell ranges;
 //   phase 1 works on whole x-rows: the populations a row receives from x -/+ 1
 //   are loaded aligned into LDS and read back shifted (with the periodic wrap
@@ -84,20 +85,20 @@ struct Shifted {
 };
 
 // Phase 0 of cells c0 .. c0+C-1 (all fluid): read own slots, collide, write
-// f*_i into slot opp(i).  PS is the population stride (a multiple of 64
-// elements) and c0 % C == 0.
+// f*_i into slot opp(i).  L places the populations (C consecutive cells of a
+// population are adjacent: c0 % C == 0 and C divides the chunk size).
 template <int Q, typename S, bool SHIFT, int C>
-__device__ __forceinline__ void fluid_cells_p0(S* __restrict__ pop, uint32_t PS, uint32_t c0,
+__device__ __forceinline__ void fluid_cells_p0(S* __restrict__ pop, const PopIndex& L, uint32_t c0,
                                                const StepParams<typename Store<S>::T>& p) {
   using T = typename Store<S>::T;
   using V = Vel<Q>;
-  using L = Lane<S, C>;
-  using R = typename L::raw;
-  const uint32_t lo = c0 * (uint32_t)sizeof(S);
+  using W = Lane<S, C>;
+  using R = typename W::raw;
+  const uint32_t lo = L.cell(c0) * (uint32_t)sizeof(S);
   S sv[Q][C];
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    L::unpack(__builtin_nontemporal_load(at_byte<R>(pop + (size_t)i * PS, lo)), sv[i]);
+    W::unpack(__builtin_nontemporal_load(at_byte<R>(pop + (size_t)i * L.pstride, lo)), sv[i]);
 #pragma unroll
   for (int k = 0; k < C; ++k) {
     T f[Q];
@@ -110,37 +111,37 @@ __device__ __forceinline__ void fluid_cells_p0(S* __restrict__ pop, uint32_t PS,
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    __builtin_nontemporal_store(L::pack(sv[i]), at_byte<R>(pop + (size_t)i * PS, lo));
+    __builtin_nontemporal_store(W::pack(sv[i]), at_byte<R>(pop + (size_t)i * L.pstride, lo));
 }
 
 // Phase 1 of x-row `row` (= y + ny z) of a fully fluid periodic lattice, lane
-// t covering cells x = C t .. C t + C - 1.  PS: population stride; tile:
+// t covering cells x = C t .. C t + C - 1.  L places the populations; tile:
 // NS * nx values of LDS for this row.  Contains block barriers: every thread
 // of the block must call it (inactive lanes with active = false).  nx % C == 0.
 template <int Q, typename S, bool SHIFT, int C>
 __device__ __forceinline__ void fluid_rows_p1(S* __restrict__ pop, int nx, int ny, int nz,
-                                              uint32_t PS, int row, bool active, int t, S* tile,
+                                              const PopIndex& L, int row, bool active, int t, S* tile,
                                               const StepParams<typename Store<S>::T>& p) {
   using T = typename Store<S>::T;
   using V = Vel<Q>;
-  using L = Lane<S, C>;
+  using W = Lane<S, C>;
   const int y = active ? row % ny : 0;
   const int z = active ? row / ny : 0;
   const int Y[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
   const int Z[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
   const int x0 = C * t;
 
-  using R = typename L::raw;
+  using R = typename W::raw;
   S sv[Q][C];
   if (active) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const uint32_t off = (uint32_t)nx * (uint32_t)(Y[1 - V::cy[i]] + ny * Z[1 - V::cz[i]]) + x0;
-      const R r = __builtin_nontemporal_load(at_byte<R>(pop + (size_t)V::opp[i] * PS, off * (uint32_t)sizeof(S)));
+      const uint32_t off = L.cell((uint32_t)nx * (uint32_t)(Y[1 - V::cy[i]] + ny * Z[1 - V::cz[i]]) + x0);
+      const R r = __builtin_nontemporal_load(at_byte<R>(pop + (size_t)V::opp[i] * L.pstride, off * (uint32_t)sizeof(S)));
       if (V::cx[i] == 0)
-        L::unpack(r, sv[i]);
+        W::unpack(r, sv[i]);
       else
-        *(typename L::raw*)(tile + Shifted<Q>::rank(i) * nx + x0) = r;
+        *(typename W::raw*)(tile + Shifted<Q>::rank(i) * nx + x0) = r;
     }
   }
   __syncthreads();
@@ -170,8 +171,8 @@ __device__ __forceinline__ void fluid_rows_p1(S* __restrict__ pop, int nx, int n
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       if (V::cx[i] == 0) {
-        const uint32_t off = (uint32_t)nx * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]) + x0;
-        __builtin_nontemporal_store(L::pack(sv[i]), at_byte<R>(pop + (size_t)i * PS, off * (uint32_t)sizeof(S)));
+        const uint32_t off = L.cell((uint32_t)nx * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]) + x0);
+        __builtin_nontemporal_store(W::pack(sv[i]), at_byte<R>(pop + (size_t)i * L.pstride, off * (uint32_t)sizeof(S)));
       } else {
 #pragma unroll
         for (int k = 0; k < C; ++k) {
@@ -187,9 +188,9 @@ __device__ __forceinline__ void fluid_rows_p1(S* __restrict__ pop, int nx, int n
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       if (V::cx[i] == 0) continue;
-      const uint32_t off = (uint32_t)nx * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]) + x0;
+      const uint32_t off = L.cell((uint32_t)nx * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]) + x0);
       __builtin_nontemporal_store(*(const R*)(tile + Shifted<Q>::rank(i) * nx + x0),
-                                  at_byte<R>(pop + (size_t)i * PS, off * (uint32_t)sizeof(S)));
+                                  at_byte<R>(pop + (size_t)i * L.pstride, off * (uint32_t)sizeof(S)));
     }
   }
 }
@@ -233,28 +234,30 @@ __device__ __forceinline__ void shift_along_row(S (&v)[C], int s, int left, int 
 // (`left` / `right`: the lanes holding row positions t - 1 and t + 1, wrapped).
 // Every access is an aligned, non-temporal row segment; populations with
 // c_x != 0 move one cell between lanes in registers after loading and before
-// storing, so no LDS tile and no barrier is needed.
+// storing, so no LDS tile and no barrier is needed.  A row must not straddle
+// two chunks of L (nx divides the chunk size), so that a row's slots are
+// addressed from the row start plus x.
 template <int Q, typename S, bool SHIFT, int C>
 __device__ __forceinline__ void fluid_rows_p1_wave(S* __restrict__ pop, int nx, int ny, int nz,
-                                                   uint32_t PS, int row, int t, int left,
+                                                   const PopIndex& L, int row, int t, int left,
                                                    int right,
                                                    const StepParams<typename Store<S>::T>& p) {
   using T = typename Store<S>::T;
   using V = Vel<Q>;
-  using L = Lane<S, C>;
+  using W = Lane<S, C>;
   const int y = row % ny;
   const int z = row / ny;
   const int Y[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
   const int Z[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
-  using R = typename L::raw;
+  using R = typename W::raw;
   const uint32_t x0 = (uint32_t)(C * t);
 
   // incoming: f_i(x) = A[opp(i)][x - c_i]
   S sv[Q][C];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const uint32_t r = (uint32_t)nx * (uint32_t)(Y[1 - V::cy[i]] + ny * Z[1 - V::cz[i]]);
-    L::unpack(__builtin_nontemporal_load(at_byte<R>(pop + (size_t)V::opp[i] * PS, (r + x0) * (uint32_t)sizeof(S))), sv[i]);
+    const uint32_t r = L.cell((uint32_t)nx * (uint32_t)(Y[1 - V::cy[i]] + ny * Z[1 - V::cz[i]]));
+    W::unpack(__builtin_nontemporal_load(at_byte<R>(pop + (size_t)V::opp[i] * L.pstride, (r + x0) * (uint32_t)sizeof(S))), sv[i]);
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i)
@@ -275,8 +278,8 @@ __device__ __forceinline__ void fluid_rows_p1_wave(S* __restrict__ pop, int nx, 
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (V::cx[i] != 0) shift_along_row<S, C>(sv[i], V::cx[i], left, right);
-    const uint32_t r = (uint32_t)nx * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]);
-    __builtin_nontemporal_store(L::pack(sv[i]), at_byte<R>(pop + (size_t)i * PS, (r + x0) * (uint32_t)sizeof(S)));
+    const uint32_t r = L.cell((uint32_t)nx * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]));
+    __builtin_nontemporal_store(W::pack(sv[i]), at_byte<R>(pop + (size_t)i * L.pstride, (r + x0) * (uint32_t)sizeof(S)));
   }
 }
 

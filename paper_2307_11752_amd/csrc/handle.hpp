@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <string>
 
+#include "lattice.hpp"
 #include "lbm.h"
 
 constexpr int RED_BLOCKS = 1024;
@@ -37,6 +38,31 @@ inline int qof(int d) { return d == LBM_D2Q9 ? 9 : 19; }
 // 64 elements, so that every array starts on a 256-byte boundary whatever N is.
 inline size_t pop_stride(size_t N) { return (N + 63) & ~size_t(63); }
 
+// Chunk size of the blocked placement, in bytes per population run.  Probes
+// of the phase-0 access pattern on MI355X (TGV 256^3, FP32): arrays 421-432
+// us, chunks of 2048 / 4096 / 8192 / 16384 / 32768 cells 395 / 392 / 387 /
+// 404 / 410 us (a streaming copy of the same bytes: 384 us).
+constexpr size_t POP_CHUNK_BYTES = 32768;
+
+// The placement of a lattice's populations: blocked when the lattice spans
+// more than one chunk and the whole buffer stays below 2^32 bytes (so every
+// byte offset fits 32 bits), else one array per population.
+inline lbm::PopIndex pop_index(int q, size_t N, size_t s) {
+  const size_t B = POP_CHUNK_BYTES / s;
+  uint32_t lb = 0;
+  while (((size_t)1 << lb) < B) ++lb;
+  const size_t chunks = (N + B - 1) / B;
+  if (N > B && (size_t)q * chunks * B * s < ((size_t)1 << 32))
+    return lbm::PopIndex{lb, (uint32_t)(B - 1), (uint32_t)(q * B), (uint32_t)B};
+  return lbm::PopIndex{31u, 0x7fffffffu, 0u, (uint32_t)pop_stride(N)};
+}
+
+// Elements the placement spans.
+inline size_t pop_elements(int q, const lbm::PopIndex& L, size_t N) {
+  if (L.bstride) return (size_t)L.bstride * ((N + L.mask) >> L.lb);
+  return (size_t)q * L.pstride;
+}
+
 inline size_t storage_bytes(int s) {
   switch (s) {
     case LBM_STORE_F64: return 8;
@@ -54,7 +80,7 @@ inline size_t storage_bytes(int s) {
 struct lbm_lattice {
   int desc = 0, q = 0, nx = 0, ny = 0, nz = 0;
   size_t N = 0;
-  size_t ps = 0;  // population stride in elements (pop_stride(N))
+  lbm::PopIndex pix{};  // placement of the populations (pop_index)
   int storage = 0;
   bool shifted = false;
   double tau = 0.0, omega = 0.0;

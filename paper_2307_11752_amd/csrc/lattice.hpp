@@ -169,6 +169,26 @@ __device__ __forceinline__ void store_nt<bf16s>(bf16s* p, float v) {
 constexpr uint32_t LINK_FLUID = 1u << 31;
 constexpr uint32_t LINK_HAS_MOVING = 1u << 30;
 
+// Placement of the populations in the buffer: population i of cell c sits at
+// element i * pstride + (c >> lb) * bstride + (c & mask).
+//   blocked: the cells fall into chunks of 2^lb; a chunk holds the q runs of
+//            its populations back to back (pstride = 2^lb, bstride = q 2^lb),
+//            so the slots a run of cells touches lie close together in HBM;
+//   arrays:  one array per population (lb = 31, mask = 2^31 - 1, bstride = 0:
+//            the chunk term vanishes for every cell index, pstride = N
+//            rounded up to 64).
+// Offsets are 32-bit: the whole buffer holds fewer than 2^32 elements, and a
+// blocked buffer fewer than 2^32 bytes.
+struct PopIndex {
+  uint32_t lb, mask, bstride, pstride;
+  __host__ __device__ __forceinline__ uint32_t cell(uint32_t c) const {
+    return (c >> lb) * bstride + (c & mask);
+  }
+  __host__ __device__ __forceinline__ uint32_t at(int i, uint32_t c) const {
+    return (uint32_t)i * pstride + cell(c);
+  }
+};
+
 template <typename T>
 struct StepParams {
   T base;       // stored value of 1.0 (Store<S>::unit): the rest density of shifted storage

@@ -2,7 +2,7 @@
 // collide-and-stream step with bounce-back walls, moving walls, periodic wrap
 // and Guo forcing.
 //
-// Propagation: in-place AA pattern on one structure-of-arrays population
+// Propagation: in-place AA pattern on one population
 // buffer.  The stream equation of the guide (f_i(t+1, x+c_i) = f*_i(t, x),
 // Introduction, "Lattice Boltzmann Methods") is realised without a second
 // lattice by alternating two kernels:
@@ -81,7 +81,7 @@ struct RawReg<double> {
 template <int Q, typename S, bool SHIFT, int PHASE, bool MASKED>
 __global__ void __launch_bounds__(256)
     step_kernel(S* __restrict__ pop, const uint32_t* __restrict__ link,
-                const uint32_t* __restrict__ mov, int nx, int ny, int nz, uint32_t PS, int nxb,
+                const uint32_t* __restrict__ mov, int nx, int ny, int nz, PopIndex L, int nxb,
                 StepParams<typename Store<S>::T> p) {
   using T = typename Store<S>::T;
   using V = Vel<Q>;
@@ -109,14 +109,14 @@ __global__ void __launch_bounds__(256)
     lw = link[idx];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const uint32_t off = (uint32_t)V::opp[i] * PS + nb.at(-V::cx[i], -V::cy[i], -V::cz[i]);
+      const uint32_t off = L.at(V::opp[i], nb.at(-V::cx[i], -V::cy[i], -V::cz[i]));
       raw[i] = V::cx[i] == 0 ? RawReg<S>::load_nt(pop + off) : RawReg<S>::load(pop + off);
     }
     if (!(lw & LINK_FLUID)) return;
     if (p.has_moving && (lw & LINK_HAS_MOVING)) mv = mov[idx];
 #pragma unroll
     for (int i = 1; i < Q; ++i)
-      if ((lw >> (V::opp[i] - 1)) & 1u) raw[i] = RawReg<S>::load(pop + (uint32_t)i * PS + idx);
+      if ((lw >> (V::opp[i] - 1)) & 1u) raw[i] = RawReg<S>::load(pop + L.at(i, idx));
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = RawReg<S>::cvt(raw[i]);
   } else {
@@ -129,9 +129,9 @@ __global__ void __launch_bounds__(256)
     for (int i = 0; i < Q; ++i) {
       uint32_t off;
       if (PHASE == 0)
-        off = (uint32_t)i * PS + idx;
+        off = L.at(i, idx);
       else
-        off = (uint32_t)V::opp[i] * PS + nb.at(-V::cx[i], -V::cy[i], -V::cz[i]);
+        off = L.at(V::opp[i], nb.at(-V::cx[i], -V::cy[i], -V::cz[i]));
       // Streaming data is touched once per launch: x-aligned accesses bypass
       // the caches; x-shifted ones (phase 1, c_x != 0) share lines with the
       // neighbouring wave and stay cached.
@@ -150,10 +150,10 @@ __global__ void __launch_bounds__(256)
     if (MASKED && i > 0 && ((mv >> (i - 1)) & 1u)) v -= rho * p.mw[i];
     uint32_t off;
     if (PHASE == 0) {
-      off = (uint32_t)V::opp[i] * PS + idx;
+      off = L.at(V::opp[i], idx);
     } else {
-      off = (uint32_t)i * PS + nb.at(V::cx[i], V::cy[i], V::cz[i]);
-      if (MASKED && i > 0 && ((lw >> (i - 1)) & 1u)) off = (uint32_t)V::opp[i] * PS + idx;
+      off = L.at(i, nb.at(V::cx[i], V::cy[i], V::cz[i]));
+      if (MASKED && i > 0 && ((lw >> (i - 1)) & 1u)) off = L.at(V::opp[i], idx);
     }
     if (PHASE == 0 || V::cx[i] == 0)
       store_nt<S>(pop + off, v);
@@ -176,16 +176,16 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 template <int Q, typename S, bool SHIFT, int C>
 __global__ void __launch_bounds__(256)
-    step_p0_flat_kernel(S* __restrict__ pop, uint32_t N, uint32_t PS,
+    step_p0_flat_kernel(S* __restrict__ pop, uint32_t N, PopIndex L,
                         StepParams<typename Store<S>::T> p) {
   const uint32_t c0 = (uint32_t)C * (blockIdx.x * blockDim.x + threadIdx.x);
   if (c0 >= N) return;
-  fluid_cells_p0<Q, S, SHIFT, C>(pop, PS, c0, p);
+  fluid_cells_p0<Q, S, SHIFT, C>(pop, L, c0, p);
 }
 
 template <int Q, typename S, bool SHIFT>
 __global__ void __launch_bounds__(256)
-    step_p1_rows_kernel(S* __restrict__ pop, int nx, int ny, int nz, uint32_t N, int tpr,
+    step_p1_rows_kernel(S* __restrict__ pop, int nx, int ny, int nz, PopIndex L, int tpr,
                         int rows_per_block, StepParams<typename Store<S>::T> p) {
   constexpr int C = Pack8<S>::C;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(256)
   const int t = (int)threadIdx.x - rloc * tpr;
   const int row = (int)blockIdx.x * rows_per_block + rloc;
   S* tile = (S*)smem_raw + (size_t)rloc * Shifted<Q>::count() * nx;
-  fluid_rows_p1<Q, S, SHIFT, C>(pop, nx, ny, nz, N, row, row < ny * nz, t, tile, p);
+  fluid_rows_p1<Q, S, SHIFT, C>(pop, nx, ny, nz, L, row, row < ny * nz, t, tile, p);
 }
 
 // Phase 1 with each x-row held by 2^lr_log2 = nx / C lanes of one wave (a
@@ -203,14 +203,14 @@ __global__ void __launch_bounds__(256)
 // scalar and the lanes only carry their x offset.
 template <int Q, typename S, bool SHIFT, int C, bool ONE_ROW>
 __global__ void __launch_bounds__(256)
-    step_p1_wave_kernel(S* __restrict__ pop, int nx, int ny, int nz, uint32_t PS, int lr_log2,
+    step_p1_wave_kernel(S* __restrict__ pop, int nx, int ny, int nz, PopIndex L, int lr_log2,
                         StepParams<typename Store<S>::T> p) {
   const int lane = (int)(threadIdx.x & 63u);
   const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if constexpr (ONE_ROW) {
     const int row = __builtin_amdgcn_readfirstlane(wave);
     if (row >= ny * nz) return;
-    fluid_rows_p1_wave<Q, S, SHIFT, C>(pop, nx, ny, nz, PS, row, lane, (lane - 1) & 63,
+    fluid_rows_p1_wave<Q, S, SHIFT, C>(pop, nx, ny, nz, L, row, lane, (lane - 1) & 63,
                                        (lane + 1) & 63, p);
   } else {
     const int lr = 1 << lr_log2;
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(256)
     const int first = lane - t;
     const int row = (wave << (6 - lr_log2)) + (lane >> lr_log2);
     if (row >= ny * nz) return;  // whole rows drop out together
-    fluid_rows_p1_wave<Q, S, SHIFT, C>(pop, nx, ny, nz, PS, row, t, first + ((t - 1) & (lr - 1)),
+    fluid_rows_p1_wave<Q, S, SHIFT, C>(pop, nx, ny, nz, L, row, t, first + ((t - 1) & (lr - 1)),
                                        first + ((t + 1) & (lr - 1)), p);
   }
 }
@@ -255,7 +255,7 @@ struct LinkVec {
 template <int Q, typename S, bool SHIFT>
 __global__ void __launch_bounds__(256)
     step_p0_masked_kernel(S* __restrict__ pop, const uint32_t* __restrict__ link,
-                          const uint32_t* __restrict__ mov, uint32_t N, uint32_t PS,
+                          const uint32_t* __restrict__ mov, uint32_t N, PopIndex L,
                           StepParams<typename Store<S>::T> p) {
   using T = typename Store<S>::T;
   using V = Vel<Q>;
@@ -266,11 +266,11 @@ __global__ void __launch_bounds__(256)
   // before issuing the population loads would expose one memory latency per wave
   uint32_t lw[C];
   LinkVec<C>::load(link + c0, lw);
-  const uint32_t lo = c0 * (uint32_t)sizeof(S);
+  const uint32_t lo = L.cell(c0) * (uint32_t)sizeof(S);
   S sv[Q][C];
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    Pack8<S>::unpack(__builtin_nontemporal_load(at_byte<raw8>(pop + (size_t)i * PS, lo)), sv[i]);
+    Pack8<S>::unpack(__builtin_nontemporal_load(at_byte<raw8>(pop + (size_t)i * L.pstride, lo)), sv[i]);
 #pragma unroll
   for (int k = 0; k < C; ++k) {
     if (!(lw[k] & LINK_FLUID)) continue;
@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(256)
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    __builtin_nontemporal_store(Pack8<S>::pack(sv[i]), at_byte<raw8>(pop + (size_t)i * PS, lo));
+    __builtin_nontemporal_store(Pack8<S>::pack(sv[i]), at_byte<raw8>(pop + (size_t)i * L.pstride, lo));
 }
 
 // ---------------------------------------------------------------------------
@@ -296,12 +296,12 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 template <int Q, typename S>
 __device__ __forceinline__ S load_phase(const S* pop, uint32_t lw, int i, uint32_t idx,
-                                        const Nbr& nb, int phase, uint32_t PS) {
+                                        const Nbr& nb, int phase, const PopIndex& L) {
   using V = Vel<Q>;
-  if (phase == 0 || i == 0) return pop[(uint32_t)i * PS + idx];
+  if (phase == 0 || i == 0) return pop[L.at(i, idx)];
   const int o = V::opp[i];
-  if ((lw >> (o - 1)) & 1u) return pop[(uint32_t)i * PS + idx];
-  return pop[(uint32_t)o * PS + nb.at(-V::cx[i], -V::cy[i], -V::cz[i])];
+  if ((lw >> (o - 1)) & 1u) return pop[L.at(i, idx)];
+  return pop[L.at(o, nb.at(-V::cx[i], -V::cy[i], -V::cz[i]))];
 }
 
 __device__ __forceinline__ void cell_coords(uint32_t idx, int nx, int ny, int& x, int& y, int& z) {
@@ -315,7 +315,7 @@ __device__ __forceinline__ void cell_coords(uint32_t idx, int nx, int ny, int& x
 template <int Q, typename S, bool SHIFT>
 __global__ void get_pop_kernel(const S* __restrict__ pop, const uint32_t* __restrict__ link,
                                double* __restrict__ out, int nx, int ny, int nz, uint32_t N,
-                               uint32_t PS, int phase) {
+                               PopIndex L, int phase) {
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
        idx += gridDim.x * blockDim.x) {
     const uint32_t lw = link[idx];
@@ -326,7 +326,7 @@ __global__ void get_pop_kernel(const S* __restrict__ pop, const uint32_t* __rest
     for (int i = 0; i < Q; ++i) {
       double v = 0.0;
       if (lw & LINK_FLUID) {
-        v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, PS));
+        v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, L));
         if (SHIFT) v += weight<Q, double>(i);
       }
       out[(size_t)i * N + idx] = v;
@@ -337,14 +337,14 @@ __global__ void get_pop_kernel(const S* __restrict__ pop, const uint32_t* __rest
 // Populations from double natural layout; phase becomes 0.
 template <int Q, typename S, bool SHIFT>
 __global__ void set_pop_kernel(S* __restrict__ pop, const double* __restrict__ in, uint32_t N,
-                               uint32_t PS) {
+                               PopIndex L) {
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
        idx += gridDim.x * blockDim.x) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       double v = in[(size_t)i * N + idx];
       if (SHIFT) v -= weight<Q, double>(i);
-      pop[(size_t)i * PS + idx] = Store<S>::from_f64(v);
+      pop[L.at(i, idx)] = Store<S>::from_f64(v);
     }
   }
 }
@@ -353,7 +353,7 @@ __global__ void set_pop_kernel(S* __restrict__ pop, const double* __restrict__ i
 template <int Q, typename S, bool SHIFT>
 __global__ void init_eq_kernel(S* __restrict__ pop, const uint32_t* __restrict__ link,
                                const double* __restrict__ rho_in, const double* __restrict__ u_in,
-                               uint32_t N, uint32_t PS) {
+                               uint32_t N, PopIndex L) {
   using V = Vel<Q>;
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
        idx += gridDim.x * blockDim.x) {
@@ -369,7 +369,7 @@ __global__ void init_eq_kernel(S* __restrict__ pop, const uint32_t* __restrict__
       const double cu = V::cx[i] * u[0] + V::cy[i] * u[1] + V::cz[i] * u[2];
       double feq = w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
       if (SHIFT) feq -= w;
-      pop[(size_t)i * PS + idx] = Store<S>::from_f64(fluid ? feq : 0.0);
+      pop[L.at(i, idx)] = Store<S>::from_f64(fluid ? feq : 0.0);
     }
   }
 }
@@ -378,7 +378,7 @@ __global__ void init_eq_kernel(S* __restrict__ pop, const uint32_t* __restrict__
 template <int Q, typename S, bool SHIFT>
 __global__ void moments_kernel(const S* __restrict__ pop, const uint32_t* __restrict__ link,
                                double* __restrict__ rho_out, double* __restrict__ u_out, int nx,
-                               int ny, int nz, uint32_t N, uint32_t PS, int phase, double gx,
+                               int ny, int nz, uint32_t N, PopIndex L, int phase, double gx,
                                double gy, double gz) {
   using V = Vel<Q>;
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
@@ -392,7 +392,7 @@ __global__ void moments_kernel(const S* __restrict__ pop, const uint32_t* __rest
       double sf = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const double v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, PS));
+        const double v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, L));
         sf += v;
         j[0] += V::cx[i] * v;
         j[1] += V::cy[i] * v;
@@ -418,7 +418,7 @@ template <int Q, typename S, bool SHIFT>
 __global__ void __launch_bounds__(RED_THREADS)
     totals_partial_kernel(const S* __restrict__ pop, const uint32_t* __restrict__ link,
                           double* __restrict__ partials, int nx, int ny, int nz, uint32_t N,
-                          uint32_t PS, int phase, double gx, double gy, double gz) {
+                          PopIndex L, int phase, double gx, double gy, double gz) {
   using V = Vel<Q>;
   double acc[RED_FIELDS] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
@@ -431,7 +431,7 @@ __global__ void __launch_bounds__(RED_THREADS)
     double sf = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const double v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, PS));
+      const double v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, L));
       sf += v;
       j[0] += V::cx[i] * v;
       j[1] += V::cy[i] * v;
@@ -668,7 +668,7 @@ template <int Q, typename S, bool SHIFT>
 struct Ops {
   using T = typename Store<S>::T;
 
-  static void launch_p1_wave(lbm_lattice* h, S* pop, uint32_t PS, int lrw, const StepParams<T>& p) {
+  static void launch_p1_wave(lbm_lattice* h, S* pop, PopIndex L, int lrw, const StepParams<T>& p) {
     if constexpr (sizeof(S) == 2) {
       constexpr int C = Pack8<S>::C;
       const unsigned threads = 128;
@@ -678,10 +678,10 @@ struct Ops {
       const unsigned nb = (unsigned)((waves * 64 + threads - 1) / threads);
       if (lrw == 6)
         hipLaunchKernelGGL((step_p1_wave_kernel<Q, S, SHIFT, C, true>), dim3(nb), dim3(threads), lds,
-                           h->stream, pop, h->nx, h->ny, h->nz, PS, lrw, p);
+                           h->stream, pop, h->nx, h->ny, h->nz, L, lrw, p);
       else
         hipLaunchKernelGGL((step_p1_wave_kernel<Q, S, SHIFT, C, false>), dim3(nb), dim3(threads),
-                           lds, h->stream, pop, h->nx, h->ny, h->nz, PS, lrw, p);
+                           lds, h->stream, pop, h->nx, h->ny, h->nz, L, lrw, p);
     }
   }
 
@@ -693,55 +693,57 @@ struct Ops {
     const uint32_t* mov = (const uint32_t*)(h->aux + h->lay.mov);
     const dim3 grid((unsigned)(h->nxb * h->ny * h->nz)), block((unsigned)h->bx);
     const uint32_t N = (uint32_t)h->N;
-    const uint32_t PS = (uint32_t)h->ps;
+    const PopIndex L = h->pix;
     constexpr int C = Pack8<S>::C;  // cells per 8-byte lane
     const int tpr = h->nx / C;
-    // 16-bit storage: rows of nx = 4 * 2^k <= 256 cells fit one wave
-    const int lrw = sizeof(S) == 2 ? wave_row_log2(h->nx, C) : -1;
+    // 16-bit storage: rows of nx = 4 * 2^k <= 256 cells fit one wave (and
+    // never straddle two chunks of the blocked placement)
+    const bool rows_whole = L.bstride == 0 || (L.mask + 1u) % (uint32_t)h->nx == 0;
+    const int lrw = sizeof(S) == 2 && rows_whole ? wave_row_log2(h->nx, C) : -1;
     if (h->all_fluid && (lrw >= 0 || (h->nx % C == 0 && tpr <= 256))) {
       // fully fluid fast path (measured launch shapes): phase 0 over flat
-      // cell ranges, 256 threads, three blocks per CU; phase 1 on whole rows,
+      // cell ranges, 128 threads, four blocks per CU; phase 1 on whole rows,
       // one wave per row for 16-bit storage (128 threads, four blocks per CU),
       // else through the LDS row tile (three blocks per CU)
       if (phase == 0) {
-        const unsigned threads = 256;
+        const unsigned threads = 128;
         const unsigned nb = (unsigned)((h->N / C + threads - 1) / threads);
         hipLaunchKernelGGL((step_p0_flat_kernel<Q, S, SHIFT, C>), dim3(nb), dim3(threads),
-                           occupancy_lds(h, 3, 0), h->stream, pop, N, PS, p);
+                           occupancy_lds(h, 4, 0), h->stream, pop, N, L, p);
       } else if (lrw >= 0) {
-        launch_p1_wave(h, pop, PS, lrw, p);
+        launch_p1_wave(h, pop, L, lrw, p);
       } else {
         const int rpb = tpr >= 256 ? 1 : 256 / tpr;
         const int rows = h->ny * h->nz;
         const unsigned nb = (unsigned)((rows + rpb - 1) / rpb);
         const size_t lds = (size_t)rpb * Shifted<Q>::count() * h->nx * sizeof(S);
         hipLaunchKernelGGL((step_p1_rows_kernel<Q, S, SHIFT>), dim3(nb), dim3(rpb * tpr),
-                           occupancy_lds(h, 3, lds), h->stream, pop, h->nx, h->ny, h->nz, PS, tpr,
+                           occupancy_lds(h, 3, lds), h->stream, pop, h->nx, h->ny, h->nz, L, tpr,
                            rpb, p);
       }
     } else if (!h->all_fluid && h->N % C == 0 && h->N >= 65536 && phase == 0) {
       // (small lattices are latency-bound: the per-cell kernel below, with
-      // more and smaller blocks, is faster there).  Four blocks per CU for
+      // more and smaller blocks, is faster there).  Six blocks per CU for
       // 4- and 8-byte storage (measured); 16-bit storage gains nothing from a cap.
       const unsigned threads = 128;
       const unsigned nb = (unsigned)((h->N / C + threads - 1) / threads);
       hipLaunchKernelGGL((step_p0_masked_kernel<Q, S, SHIFT>), dim3(nb), dim3(threads),
-                         occupancy_lds(h, sizeof(S) >= 4 ? 4 : 0, 0), h->stream, pop, link, mov, N,
-                         PS, p);
+                         occupancy_lds(h, sizeof(S) >= 4 ? 6 : 0, 0), h->stream, pop, link, mov, N,
+                         L, p);
     } else if (h->all_fluid) {
       if (phase == 0)
         hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 0, false>), grid, block, 0, h->stream, pop,
-                           link, mov, h->nx, h->ny, h->nz, PS, h->nxb, p);
+                           link, mov, h->nx, h->ny, h->nz, L, h->nxb, p);
       else
         hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 1, false>), grid, block, 0, h->stream, pop,
-                           link, mov, h->nx, h->ny, h->nz, PS, h->nxb, p);
+                           link, mov, h->nx, h->ny, h->nz, L, h->nxb, p);
     } else {
       if (phase == 0)
         hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 0, true>), grid, block, 0, h->stream, pop,
-                           link, mov, h->nx, h->ny, h->nz, PS, h->nxb, p);
+                           link, mov, h->nx, h->ny, h->nz, L, h->nxb, p);
       else
         hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 1, true>), grid, block, 0, h->stream, pop,
-                           link, mov, h->nx, h->ny, h->nz, PS, h->nxb, p);
+                           link, mov, h->nx, h->ny, h->nz, L, h->nxb, p);
     }
   }
 
@@ -753,21 +755,21 @@ struct Ops {
   static void get_pop(lbm_lattice* h, double* out) {
     hipLaunchKernelGGL((get_pop_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
                        (const S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), out, h->nx,
-                       h->ny, h->nz, (uint32_t)h->N, (uint32_t)h->ps, h->phase);
+                       h->ny, h->nz, (uint32_t)h->N, h->pix, h->phase);
   }
   static void set_pop(lbm_lattice* h, const double* in) {
     hipLaunchKernelGGL((set_pop_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
-                       (S*)h->pop, in, (uint32_t)h->N, (uint32_t)h->ps);
+                       (S*)h->pop, in, (uint32_t)h->N, h->pix);
   }
   static void init_eq(lbm_lattice* h, const double* rho, const double* u) {
     hipLaunchKernelGGL((init_eq_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
                        (S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), rho, u,
-                       (uint32_t)h->N, (uint32_t)h->ps);
+                       (uint32_t)h->N, h->pix);
   }
   static void moments(lbm_lattice* h, double* rho, double* u) {
     hipLaunchKernelGGL((moments_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
                        (const S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), rho, u, h->nx,
-                       h->ny, h->nz, (uint32_t)h->N, (uint32_t)h->ps, h->phase, h->g[0], h->g[1],
+                       h->ny, h->nz, (uint32_t)h->N, h->pix, h->phase, h->g[0], h->g[1],
                        h->g[2]);
   }
   static void totals(lbm_lattice* h) {
@@ -775,7 +777,7 @@ struct Ops {
     double* result = (double*)(h->aux + h->lay.result);
     hipLaunchKernelGGL((totals_partial_kernel<Q, S, SHIFT>), dim3(RED_BLOCKS), dim3(RED_THREADS),
                        0, h->stream, (const S*)h->pop, (const uint32_t*)(h->aux + h->lay.link),
-                       partials, h->nx, h->ny, h->nz, (uint32_t)h->N, (uint32_t)h->ps, h->phase,
+                       partials, h->nx, h->ny, h->nz, (uint32_t)h->N, h->pix, h->phase,
                        h->g[0], h->g[1], h->g[2]);
     hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(RED_THREADS), 0, h->stream, partials,
                        result, RED_BLOCKS);
@@ -842,7 +844,10 @@ lbm_status lbm_required_bytes(lbm_descriptor d, int nx, int ny, int nz, lbm_stor
   if (st) return fail(nullptr, st, why);
   if (storage_bytes(s) == 0) return fail(nullptr, LBM_ERR_ARG, "unknown storage type");
   const size_t N = (size_t)nx * ny * nz;
-  if (pop_bytes) *pop_bytes = align256((size_t)qof(d) * pop_stride(N) * storage_bytes(s));
+  if (pop_bytes) {
+    const PopIndex L = pop_index(qof(d), N, storage_bytes(s));
+    *pop_bytes = align256(pop_elements(qof(d), L, N) * storage_bytes(s));
+  }
   if (aux_bytes) *aux_bytes = aux_layout(N).total;
   return LBM_OK;
 }
@@ -888,7 +893,7 @@ lbm_status lbm_lattice_create(lbm_lattice** out, lbm_descriptor d, int nx, int n
   h->ny = ny;
   h->nz = nz;
   h->N = (size_t)nx * ny * nz;
-  h->ps = pop_stride(h->N);
+  h->pix = pop_index(h->q, h->N, storage_bytes(s));
   h->storage = s;
   h->shifted = (flags & LBM_FLAG_SHIFTED) != 0;
   h->tau = tau;

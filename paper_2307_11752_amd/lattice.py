@@ -81,7 +81,7 @@ class Lattice(_Handle):
     """One lattice (one block) on the current GPU.
 
     shape = (nx, ny, nz); populations live in a caller-owned uint8 tensor
-    ``self.pop`` of ``lbm_required_bytes`` bytes (structure of arrays).
+    ``self.pop`` of ``lbm_required_bytes`` bytes (placement: see include/lbm.h).
     """
 
     def __init__(self, descriptor, shape, tau, storage="f32", shifted=False, stream=None,

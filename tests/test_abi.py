@@ -43,9 +43,18 @@ def test_required_bytes(lib):
     assert a.value >= 8 * 256**3
     assert lib.lbm_required_bytes(0, 64, 64, 1, _lib.STORE_F64, ctypes.byref(p), ctypes.byref(a)) == 0
     assert p.value == 9 * 64 * 64 * 8
-    # population arrays are PS = N rounded up to 64 elements apart
+    # within one chunk (32 KiB of a population): one array per population,
+    # PS = N rounded up to 64 elements apart
     assert lib.lbm_required_bytes(1, 10, 10, 10, _lib.STORE_F16, ctypes.byref(p), None) == 0
     assert p.value == ((19 * 1024 * 2 + 255) // 256) * 256
+    # blocked placement: N rounded up to whole chunks of 32 KiB / s cells
+    assert lib.lbm_required_bytes(1, 100, 100, 100, _lib.STORE_F32, ctypes.byref(p), None) == 0
+    assert p.value == 19 * (-(-10**6 // 8192)) * 8192 * 4
+    assert lib.lbm_required_bytes(0, 200, 90, 1, _lib.STORE_F64, ctypes.byref(p), None) == 0
+    assert p.value == 9 * 5 * 4096 * 8
+    # 2^32 bytes or more: arrays again (32-bit byte offsets inside a blocked buffer)
+    assert lib.lbm_required_bytes(1, 608, 608, 600, _lib.STORE_F16, ctypes.byref(p), None) == 0
+    assert p.value == 19 * 608 * 608 * 600 * 2
     assert lib.lbm_required_bytes(0, 8, 8, 2, 0, ctypes.byref(p), None) == _lib.ERR_ARG
     assert lib.lbm_required_bytes(1, 0, 8, 8, 0, ctypes.byref(p), None) == _lib.ERR_ARG
     assert lib.lbm_required_bytes(1, 8, 8, 8, 9, ctypes.byref(p), None) == _lib.ERR_ARG

@@ -23,8 +23,11 @@ def lbm():
 
 from paper_2307_11752_amd import workloads as W  # noqa: E402
 
-SHAPES = [(5, 4, 3), (16, 9, 7), (7, 12, 5), (33, 3, 4), (3, 3, 3), (20, 17, 11), (64, 5, 2)]
-TAUS = [0.56, 0.8, 1.0, 0.62, 0.9, 0.7, 0.55]
+# (48, 20, 18): more cells than one chunk of the blocked placement for every
+# storage type, rows straddling chunks
+SHAPES = [(5, 4, 3), (16, 9, 7), (7, 12, 5), (33, 3, 4), (3, 3, 3), (20, 17, 11), (64, 5, 2),
+          (48, 20, 18)]
+TAUS = [0.56, 0.8, 1.0, 0.62, 0.9, 0.7, 0.55, 0.75]
 
 
 def _oracles(orc, shapes, taus, fields):

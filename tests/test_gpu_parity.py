@@ -64,8 +64,12 @@ CASES_2D = [
 # the LDS row tile with one and many rows per block, and shapes that fall
 # back to the per-cell kernel (nx not a multiple).
 FLUID_3D = [(8, 6, 5), (12, 5, 4), (64, 4, 3), (256, 3, 2), (512, 2, 3), (6, 5, 4), (20, 3, 7),
-            (256, 5, 3), (512, 3, 3)]  # a last LDS-row block half used
-FLUID_2D = [(16, 10, 1), (128, 6, 1), (36, 7, 1), (10, 9, 1)]
+            (256, 5, 3), (512, 3, 3),  # a last LDS-row block half used
+            # more cells than one chunk of the blocked placement (4096 / 8192 /
+            # 16384 cells for 8- / 4- / 2-byte storage), rows that straddle
+            # chunks, a ragged last chunk
+            (300, 30, 4), (96, 40, 9), (64, 32, 9)]
+FLUID_2D = [(16, 10, 1), (128, 6, 1), (36, 7, 1), (10, 9, 1), (200, 90, 1)]
 
 
 def _pair(orc, lbm, d, shape, periodic, tau, storage, shifted, seed, g=(0, 0, 0), uw=(0, 0, 0),
