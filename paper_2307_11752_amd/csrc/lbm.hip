@@ -704,7 +704,9 @@ struct Ops {
       // fully fluid fast path (measured launch shapes): phase 0 over flat
       // cell ranges, 128 threads, four blocks per CU; phase 1 on whole rows,
       // one wave per row for 16-bit storage (128 threads, four blocks per CU),
-      // else through the LDS row tile (three blocks per CU)
+      // else through the LDS row tile (blocks of whole rows, about 128 threads
+      // and four blocks per CU; rows wider than 128 lanes one per block, three
+      // blocks per CU)
       if (phase == 0) {
         const unsigned threads = 128;
         const unsigned nb = (unsigned)((h->N / C + threads - 1) / threads);
@@ -713,13 +715,13 @@ struct Ops {
       } else if (lrw >= 0) {
         launch_p1_wave(h, pop, L, lrw, p);
       } else {
-        const int rpb = tpr >= 256 ? 1 : 256 / tpr;
+        const int rpb = tpr >= 128 ? 1 : 128 / tpr;
         const int rows = h->ny * h->nz;
         const unsigned nb = (unsigned)((rows + rpb - 1) / rpb);
         const size_t lds = (size_t)rpb * Shifted<Q>::count() * h->nx * sizeof(S);
         hipLaunchKernelGGL((step_p1_rows_kernel<Q, S, SHIFT>), dim3(nb), dim3(rpb * tpr),
-                           occupancy_lds(h, 3, lds), h->stream, pop, h->nx, h->ny, h->nz, L, tpr,
-                           rpb, p);
+                           occupancy_lds(h, rpb * tpr <= 128 ? 4 : 3, lds), h->stream, pop, h->nx,
+                           h->ny, h->nz, L, tpr, rpb, p);
       }
     } else if (!h->all_fluid && h->N % C == 0 && h->N >= 65536 && phase == 0) {
       // (small lattices are latency-bound: the per-cell kernel below, with

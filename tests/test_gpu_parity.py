@@ -63,8 +63,9 @@ CASES_2D = [
 # the shapes cover rows held by part of a wave or one wave (16-bit storage),
 # the LDS row tile with one and many rows per block, and shapes that fall
 # back to the per-cell kernel (nx not a multiple).
-FLUID_3D = [(8, 6, 5), (12, 5, 4), (64, 4, 3), (256, 3, 2), (512, 2, 3), (6, 5, 4), (20, 3, 7),
-            (256, 5, 3), (512, 3, 3),  # a last LDS-row block half used
+FLUID_3D = [(8, 6, 5), (12, 5, 4), (64, 4, 3), (256, 3, 2), (512, 2, 3), (6, 5, 4),
+            (20, 3, 7),  # FP32: 12 rows of 10 lanes per LDS-row block, the last one 9 rows
+            (256, 5, 3), (512, 3, 3),
             # more cells than one chunk of the blocked placement (4096 / 8192 /
             # 16384 cells for 8- / 4- / 2-byte storage), rows that straddle
             # chunks, a ragged last chunk
