@@ -32,7 +32,7 @@ struct BatchLat {
   uint32_t N;  // cells
   PopIndex pix;  // placement of the lattice's populations
   double omega;
-  int c;    // cells per lane: 8 bytes' worth when nx allows it, else 1
+  int c;    // phase-1 cells per lane (row_lane_cells); phase 0 always moves 8 bytes a lane
   int tpr;  // lanes per x-row = nx / c
 };
 
@@ -67,13 +67,11 @@ __global__ void __launch_bounds__(512)
     p.kguo = (T)(1.0 - 0.5 * L.omega);
     S* pop = base + L.pop_off;
     if (PHASE == 0) {
-      const uint32_t c0 = item.first + (uint32_t)L.c * threadIdx.x;
-      if (c0 < item.first + item.count) {
-        if (L.c == CM)
-          fluid_cells_p0<Q, S, SHIFT, CM>(pop, L.pix, c0, p);
-        else
-          fluid_cells_p0<Q, S, SHIFT, 1>(pop, L.pix, c0, p);
-      }
+      // 8 bytes a lane whatever nx is: phase 0 is local to each cell, and a
+      // lane that runs past the last cell only touches padding slots (the
+      // population runs are padded to a multiple of 64 cells or whole chunks)
+      const uint32_t c0 = item.first + (uint32_t)CM * threadIdx.x;
+      if (c0 < item.first + item.count) fluid_cells_p0<Q, S, SHIFT, CM>(pop, L.pix, c0, p);
     } else {
       const int rloc = (int)threadIdx.x / L.tpr;
       const int t = (int)threadIdx.x - rloc * L.tpr;
@@ -82,6 +80,9 @@ __global__ void __launch_bounds__(512)
       S* tile = (S*)smem_raw + (size_t)rloc * Shifted<Q>::count() * L.nx;
       if (L.c == CM)
         fluid_rows_p1<Q, S, SHIFT, CM>(pop, L.nx, L.ny, L.nz, L.pix, row, active, t, tile, p);
+      else if (CM == 4 && L.c == 2)
+        fluid_rows_p1<Q, S, SHIFT, CM == 4 ? 2 : 1>(pop, L.nx, L.ny, L.nz, L.pix, row, active, t,
+                                                    tile, p);
       else
         fluid_rows_p1<Q, S, SHIFT, 1>(pop, L.nx, L.ny, L.nz, L.pix, row, active, t, tile, p);
       __syncthreads();  // the next item reuses the LDS tile
@@ -119,6 +120,15 @@ LaunchFn launcher(int q, int storage, bool shifted) {
   return shifted ? launch_for_storage<19, true>(storage) : launch_for_storage<19, false>(storage);
 }
 
+// Phase-1 cells per lane for rows of nx cells in s-byte storage: the widest
+// aligned lane (8, then 4 bytes) whose cell count divides nx, else 1.
+int row_lane_cells(int nx, size_t s) {
+  const int cmax = 8 / (int)s;
+  if (nx % cmax == 0) return cmax;
+  if (cmax == 4 && nx % 2 == 0) return 2;
+  return 1;
+}
+
 constexpr int MIN_THREADS = 128;  // smallest block; sizes the phase-0 item table
 constexpr int MAX_THREADS = 512;
 const int THREAD_CHOICES[] = {128, 256, 512};
@@ -153,8 +163,7 @@ lbm_status batch_layout(lbm_descriptor d, int count, const int* dims, lbm_storag
     pop += pb;  // each part is a multiple of 256 bytes
     aux += ab;
     const size_t N = (size_t)dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
-    const int cmax = 8 / (int)storage_bytes(s);
-    const int lanes = dims[3 * b] % cmax == 0 ? dims[3 * b] / cmax : dims[3 * b];
+    const int lanes = dims[3 * b] / row_lane_cells(dims[3 * b], storage_bytes(s));
     if (lanes > MAX_THREADS) {
       *why = "lattice " + std::to_string(b) + ": an x-row needs " + std::to_string(lanes) +
              " lanes, more than " + std::to_string(MAX_THREADS);
@@ -217,7 +226,7 @@ void drop_batch_graph(lbm_batch* b) {
   }
 }
 
-// Cut every lattice into phase-0 items (runs of threads * c cells) and
+// Cut every lattice into phase-0 items (runs of threads lanes of 8 bytes) and
 // phase-1 items (as many whole x-rows as threads lanes hold).
 lbm_status build_items(lbm_batch* b, int threads) {
   if (threads < b->max_tpr)
@@ -229,7 +238,7 @@ lbm_status build_items(lbm_batch* b, int threads) {
   for (int l = 0; l < b->count; ++l) {
     const BatchLat& L = b->lats[l];
     BatchItem it{L.pop_off, L.omega, L.N, L.pix, L.nx, L.ny, L.nz, L.c, L.tpr, 0, 0};
-    const uint32_t chunk = (uint32_t)threads * (uint32_t)L.c;
+    const uint32_t chunk = (uint32_t)threads * (uint32_t)(8 / storage_bytes(b->storage));
     for (uint32_t c = 0; c < L.N; c += chunk) {
       it.first = c;
       it.count = std::min<uint32_t>(chunk, L.N - c);
@@ -368,8 +377,7 @@ lbm_status lbm_batch_create(lbm_batch** out, lbm_descriptor d, int count, const 
     bl.N = (uint32_t)v->N;
     bl.pix = v->pix;
     bl.omega = v->omega;
-    const int cmax = 8 / (int)storage_bytes(s);
-    bl.c = nx % cmax == 0 ? cmax : 1;
+    bl.c = row_lane_cells(nx, storage_bytes(s));
     bl.tpr = nx / bl.c;
     b->max_tpr = std::max(b->max_tpr, bl.tpr);
     b->lats.push_back(bl);

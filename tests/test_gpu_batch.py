@@ -23,11 +23,14 @@ def lbm():
 
 from paper_2307_11752_amd import workloads as W  # noqa: E402
 
-# (48, 20, 18): more cells than one chunk of the blocked placement for every
-# storage type, rows straddling chunks
+# Row lanes: nx = 16, 20, 64, 48 take 8-byte lanes in every storage, 18 takes
+# 4-byte lanes in 16-bit storage, odd nx one cell a lane.  (3, 3, 3): 27 cells,
+# so the last 8-byte phase-0 lane runs into the padding.  (48, 20, 18): more
+# cells than one chunk of the blocked placement for every storage type, rows
+# straddling chunks.
 SHAPES = [(5, 4, 3), (16, 9, 7), (7, 12, 5), (33, 3, 4), (3, 3, 3), (20, 17, 11), (64, 5, 2),
-          (48, 20, 18)]
-TAUS = [0.56, 0.8, 1.0, 0.62, 0.9, 0.7, 0.55, 0.75]
+          (48, 20, 18), (18, 7, 5)]
+TAUS = [0.56, 0.8, 1.0, 0.62, 0.9, 0.7, 0.55, 0.75, 0.65]
 
 
 def _oracles(orc, shapes, taus, fields):
