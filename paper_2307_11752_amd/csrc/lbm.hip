@@ -700,19 +700,20 @@ struct Ops {
     // never straddle two chunks of the blocked placement)
     const bool rows_whole = L.bstride == 0 || (L.mask + 1u) % (uint32_t)h->nx == 0;
     const int lrw = sizeof(S) == 2 && rows_whole ? wave_row_log2(h->nx, C) : -1;
-    if (h->all_fluid && (lrw >= 0 || (h->nx % C == 0 && tpr <= 256))) {
+    if (h->all_fluid && phase == 0) {
       // fully fluid fast path (measured launch shapes): phase 0 over flat
-      // cell ranges, 128 threads, four blocks per CU; phase 1 on whole rows,
-      // one wave per row for 16-bit storage (128 threads, four blocks per CU),
-      // else through the LDS row tile (blocks of whole rows, about 128 threads
-      // and four blocks per CU; rows wider than 128 lanes one per block, three
-      // blocks per CU)
-      if (phase == 0) {
-        const unsigned threads = 128;
-        const unsigned nb = (unsigned)((h->N / C + threads - 1) / threads);
-        hipLaunchKernelGGL((step_p0_flat_kernel<Q, S, SHIFT, C>), dim3(nb), dim3(threads),
-                           occupancy_lds(h, 4, 0), h->stream, pop, N, L, p);
-      } else if (lrw >= 0) {
+      // cell ranges whatever nx is (the last lane may run into the padding of
+      // the population runs), 128 threads, four blocks per CU
+      const unsigned threads = 128;
+      const unsigned nb = (unsigned)(((h->N + C - 1) / C + threads - 1) / threads);
+      hipLaunchKernelGGL((step_p0_flat_kernel<Q, S, SHIFT, C>), dim3(nb), dim3(threads),
+                         occupancy_lds(h, 4, 0), h->stream, pop, N, L, p);
+    } else if (h->all_fluid && (lrw >= 0 || (h->nx % C == 0 && tpr <= 256))) {
+      // phase 1 on whole rows, one wave per row for 16-bit storage (128
+      // threads, four blocks per CU), else through the LDS row tile (blocks of
+      // whole rows, about 128 threads and four blocks per CU; rows wider than
+      // 128 lanes one per block, three blocks per CU)
+      if (lrw >= 0) {
         launch_p1_wave(h, pop, L, lrw, p);
       } else {
         const int rpb = tpr >= 128 ? 1 : 128 / tpr;
@@ -732,13 +733,9 @@ struct Ops {
       hipLaunchKernelGGL((step_p0_masked_kernel<Q, S, SHIFT>), dim3(nb), dim3(threads),
                          occupancy_lds(h, sizeof(S) >= 4 ? 6 : 0, 0), h->stream, pop, link, mov, N,
                          L, p);
-    } else if (h->all_fluid) {
-      if (phase == 0)
-        hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 0, false>), grid, block, 0, h->stream, pop,
-                           link, mov, h->nx, h->ny, h->nz, L, h->nxb, p);
-      else
-        hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 1, false>), grid, block, 0, h->stream, pop,
-                           link, mov, h->nx, h->ny, h->nz, L, h->nxb, p);
+    } else if (h->all_fluid) {  // phase 1, rows the row kernels do not take
+      hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 1, false>), grid, block, 0, h->stream, pop,
+                         link, mov, h->nx, h->ny, h->nz, L, h->nxb, p);
     } else {
       if (phase == 0)
         hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 0, true>), grid, block, 0, h->stream, pop,

@@ -58,19 +58,21 @@ CASES_2D = [
     ((130, 5, 1), 0b01),
     ((272, 256, 1), 0b01),  # >= 65536 cells: masked D2Q9 takes the flat phase-0 kernel
 ]
-# Fully fluid periodic boxes take the row/flat fast path when nx is a multiple
-# of the cells per lane (8 bytes / storage size) and a row fits 256 lanes;
-# the shapes cover rows held by part of a wave or one wave (16-bit storage),
-# the LDS row tile with one and many rows per block, and shapes that fall
-# back to the per-cell kernel (nx not a multiple).
+# Fully fluid periodic boxes take the flat phase-0 kernel always, and the row
+# kernels for phase 1 when nx is a multiple of the cells per lane (8 bytes /
+# storage size) and a row fits 256 lanes; the shapes cover rows held by part
+# of a wave or one wave (16-bit storage), the LDS row tile with one and many
+# rows per block, and phase 1 falling back to the per-cell kernel (nx not a
+# multiple).
 FLUID_3D = [(8, 6, 5), (12, 5, 4), (64, 4, 3), (256, 3, 2), (512, 2, 3), (6, 5, 4),
             (20, 3, 7),  # FP32: 12 rows of 10 lanes per LDS-row block, the last one 9 rows
             (256, 5, 3), (512, 3, 3),
             # more cells than one chunk of the blocked placement (4096 / 8192 /
             # 16384 cells for 8- / 4- / 2-byte storage), rows that straddle
             # chunks, a ragged last chunk
-            (300, 30, 4), (96, 40, 9), (64, 32, 9)]
-FLUID_2D = [(16, 10, 1), (128, 6, 1), (36, 7, 1), (10, 9, 1), (200, 90, 1)]
+            (300, 30, 4), (96, 40, 9), (64, 32, 9),
+            (7, 5, 3)]  # an odd cell count: the last phase-0 lane runs into the padding
+FLUID_2D = [(16, 10, 1), (128, 6, 1), (36, 7, 1), (10, 9, 1), (200, 90, 1), (9, 7, 1)]
 
 
 def _pair(orc, lbm, d, shape, periodic, tau, storage, shifted, seed, g=(0, 0, 0), uw=(0, 0, 0),
