@@ -200,6 +200,24 @@ struct StepParams {
   int has_moving;
 };
 
+// Velocity i + H (H = (Q - 1) / 2) is the opposite of velocity i for
+// 1 <= i <= H, with the same weight.
+template <int Q>
+constexpr bool pairs_are_opposite() {
+  constexpr int H = (Q - 1) / 2;
+  for (int i = 1; i <= H; ++i)
+    if (Vel<Q>::opp[i] != i + H || Vel<Q>::cx[i + H] != -Vel<Q>::cx[i] ||
+        Vel<Q>::cy[i + H] != -Vel<Q>::cy[i] || Vel<Q>::cz[i + H] != -Vel<Q>::cz[i] ||
+        Vel<Q>::w36[i + H] != Vel<Q>::w36[i])
+      return false;
+  return true;
+}
+
+// 1 / rho: the hardware reciprocal in float (about one ulp), a division in
+// double.
+__device__ __forceinline__ float reciprocal(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double reciprocal(double v) { return 1.0 / v; }
+
 // One BGK + Guo collision of a cell held in registers (in place).
 //   rho = base + sum f  (base = p.base when f stores f_i - w_i, else 0;
 //                        p.base = 1 unless the storage holds scaled values)
@@ -207,22 +225,31 @@ struct StepParams {
 //   feq_i - base*w_i = w_i (sum f + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u))
 //   f*_i = f_i + omega (feq_i - f_i) + (1 - omega/2) w_i (3 (c_i - u).F + 9 (c_i.u)(c_i.F))
 // with F = rho g.  Returns rho.
+// Evaluated by opposite pairs (i, i + H): with A = sum f - 1.5 rho u.u, the
+// equilibrium is P + M for velocity i and P - M for its opposite, P = w_i (A +
+// 4.5 rho (c_i.u)^2) and M = 3 w_i rho c_i.u; the Guo source likewise is
+// G_P + G_M and G_P - G_M, G_P = (1 - omega/2) w_i (9 (c_i.u)(c_i.F) - 3 u.F)
+// and G_M = 3 (1 - omega/2) w_i c_i.F.  The relaxation keeps the form
+// f + omega (feq - f), whose rounding is that of the small non-equilibrium part.
 template <int Q, bool SHIFT, typename T>
 __device__ __forceinline__ T collide(T (&f)[Q], const StepParams<T>& p) {
   using V = Vel<Q>;
-  T sf = T(0), jx = T(0), jy = T(0), jz = T(0);
+  constexpr int H = (Q - 1) / 2;
+  static_assert(pairs_are_opposite<Q>(), "velocity i + H must be the opposite of velocity i");
+  T sf = f[0], jx = T(0), jy = T(0), jz = T(0);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    sf += f[i];
-    if (V::cx[i] > 0) jx += f[i];
-    if (V::cx[i] < 0) jx -= f[i];
-    if (V::cy[i] > 0) jy += f[i];
-    if (V::cy[i] < 0) jy -= f[i];
-    if (V::cz[i] > 0) jz += f[i];
-    if (V::cz[i] < 0) jz -= f[i];
+  for (int k = 1; k <= H; ++k) {
+    const T d = f[k] - f[k + H];
+    sf += f[k] + f[k + H];
+    if (V::cx[k] > 0) jx += d;
+    if (V::cx[k] < 0) jx -= d;
+    if (V::cy[k] > 0) jy += d;
+    if (V::cy[k] < 0) jy -= d;
+    if (V::cz[k] > 0) jz += d;
+    if (V::cz[k] < 0) jz -= d;
   }
   const T rho = SHIFT ? p.base + sf : sf;
-  const T inv = T(1) / rho;
+  const T inv = reciprocal(rho);
   T ux = jx * inv, uy = jy * inv, uz = jz * inv;
   if (p.has_force) {
     ux += T(0.5) * p.g[0];
@@ -232,24 +259,33 @@ __device__ __forceinline__ T collide(T (&f)[Q], const StepParams<T>& p) {
   const T uu = ux * ux + uy * uy + uz * uz;
   const T A = sf - T(1.5) * rho * uu;
   const T om = p.omega;
+  f[0] = fma(om, weight<Q, T>(0) * A - f[0], f[0]);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const T w = weight<Q, T>(i);
-    const T cu = T(V::cx[i]) * ux + T(V::cy[i]) * uy + T(V::cz[i]) * uz;
-    const T feq = w * (A + rho * cu * (T(3) + T(4.5) * cu));
-    f[i] = f[i] + om * (feq - f[i]);
+  for (int k = 1; k <= H; ++k) {
+    const T w = weight<Q, T>(k);
+    const T cu = T(V::cx[k]) * ux + T(V::cy[k]) * uy + T(V::cz[k]) * uz;
+    const T rc = rho * cu;
+    const T P = fma(T(4.5) * w * rc, cu, w * A);
+    const T M = T(3) * w * rc;
+    f[k] = fma(om, (P + M) - f[k], f[k]);
+    f[k + H] = fma(om, (P - M) - f[k + H], f[k + H]);
   }
-  // The Guo source is added in a block of its own behind a uniform branch, so
-  // that unforced lattices skip it instead of computing and discarding it.
+  // The Guo source is a block of its own behind a uniform branch, so that
+  // unforced lattices skip it instead of computing and discarding it.
   if (p.has_force) {
     const T Fx = rho * p.g[0], Fy = rho * p.g[1], Fz = rho * p.g[2];
-    const T kuF = ux * Fx + uy * Fy + uz * Fz;
+    const T uF = ux * Fx + uy * Fy + uz * Fz;
+    const T kg = p.kguo;
+    f[0] += T(-3) * kg * weight<Q, T>(0) * uF;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T w = weight<Q, T>(i);
-      const T cu = T(V::cx[i]) * ux + T(V::cy[i]) * uy + T(V::cz[i]) * uz;
-      const T cF = T(V::cx[i]) * Fx + T(V::cy[i]) * Fy + T(V::cz[i]) * Fz;
-      f[i] += p.kguo * w * (T(3) * (cF - kuF) + T(9) * cu * cF);
+    for (int k = 1; k <= H; ++k) {
+      const T kw = kg * weight<Q, T>(k);
+      const T cu = T(V::cx[k]) * ux + T(V::cy[k]) * uy + T(V::cz[k]) * uz;
+      const T cF = T(V::cx[k]) * Fx + T(V::cy[k]) * Fy + T(V::cz[k]) * Fz;
+      const T GP = fma(T(9) * kw * cu, cF, T(-3) * kw * uF);
+      const T GM = T(3) * kw * cF;
+      f[k] += GP + GM;
+      f[k + H] += GP - GM;
     }
   }
   return rho;
