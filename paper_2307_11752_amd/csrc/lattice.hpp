@@ -213,9 +213,14 @@ constexpr bool pairs_are_opposite() {
   return true;
 }
 
-// 1 / rho: the hardware reciprocal in float (about one ulp), a division in
-// double.
-__device__ __forceinline__ float reciprocal(float v) { return __builtin_amdgcn_rcpf(v); }
+// 1 / rho.  float: the hardware reciprocal (within about one ulp, and
+// biased: used as is, the bias accumulates in u over many steps) refined by
+// one Newton step, r + r (1 - v r), which leaves an error far below half an
+// ulp before the final rounding.  double: a division.
+__device__ __forceinline__ float reciprocal(float v) {
+  const float r = __builtin_amdgcn_rcpf(v);
+  return fmaf(r, fmaf(-v, r, 1.0f), r);
+}
 __device__ __forceinline__ double reciprocal(double v) { return 1.0 / v; }
 
 // One BGK + Guo collision of a cell held in registers (in place).
@@ -265,8 +270,11 @@ __device__ __forceinline__ T collide(T (&f)[Q], const StepParams<T>& p) {
     const T w = weight<Q, T>(k);
     const T cu = T(V::cx[k]) * ux + T(V::cy[k]) * uy + T(V::cz[k]) * uz;
     const T rc = rho * cu;
-    const T P = fma(T(4.5) * w * rc, cu, w * A);
-    const T M = T(3) * w * rc;
+    // w multiplies last: a folded constant such as 3 w would carry its own
+    // rounding (1/6 is not a binary fraction), a bias the odd part would add
+    // to the momentum of every collision
+    const T P = w * fma(T(4.5) * rc, cu, A);
+    const T M = w * (T(3) * rc);
     f[k] = fma(om, (P + M) - f[k], f[k]);
     f[k + H] = fma(om, (P - M) - f[k + H], f[k + H]);
   }
@@ -276,14 +284,14 @@ __device__ __forceinline__ T collide(T (&f)[Q], const StepParams<T>& p) {
     const T Fx = rho * p.g[0], Fy = rho * p.g[1], Fz = rho * p.g[2];
     const T uF = ux * Fx + uy * Fy + uz * Fz;
     const T kg = p.kguo;
-    f[0] += T(-3) * kg * weight<Q, T>(0) * uF;
+    f[0] += kg * weight<Q, T>(0) * (T(-3) * uF);
 #pragma unroll
     for (int k = 1; k <= H; ++k) {
       const T kw = kg * weight<Q, T>(k);
       const T cu = T(V::cx[k]) * ux + T(V::cy[k]) * uy + T(V::cz[k]) * uz;
       const T cF = T(V::cx[k]) * Fx + T(V::cy[k]) * Fy + T(V::cz[k]) * Fz;
-      const T GP = fma(T(9) * kw * cu, cF, T(-3) * kw * uF);
-      const T GM = T(3) * kw * cF;
+      const T GP = kw * fma(T(9) * cu, cF, T(-3) * uF);
+      const T GM = kw * (T(3) * cF);
       f[k] += GP + GM;
       f[k + H] += GP - GM;
     }
