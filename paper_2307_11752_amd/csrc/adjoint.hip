@@ -175,25 +175,51 @@ __global__ void __launch_bounds__(256)
   const CellState c = cell_state(f, d, p.g);
   const float k = 1.f - 0.5f * p.omega;
   const float F[3] = {c.rho * p.g[0], c.rho * p.g[1], c.rho * p.g[2]};
-  float G[3] = {0.f, 0.f, 0.f}, E = 0.f;
+  // G_a = sum_i mu_i (omega dfeq_i/dv_a + dS_i/dv_a) and rho E = sum_i mu_i
+  // (omega feq_i + S_i) depend on mu only through the moments of m_i = w_i mu_i:
+  // M0 = sum m_i, M1 = sum m_i c_i, M2 = sum m_i c_i c_i.  With
+  //   dfeq_i/dv_a = w_i rho (3 c_ia + 9 (c_i.v) c_ia - 3 v_a),
+  //   dS_i/dv_a   = k w_i (9 c_ia (c_i.F) - 3 F_a),
+  //   feq_i       = w_i rho (1 + 3 c_i.v + 4.5 (c_i.v)^2 - 1.5 v.v),
+  //   S_i         = k w_i (3 c_i.F - 3 v.F + 9 (c_i.v)(c_i.F)):
+  //   G   = omega rho (3 M1 + 9 M2 v - 3 M0 v) + k (9 M2 F - 3 M0 F),
+  //   rho E = omega rho (M0 (1 - 1.5 v.v) + 3 M1.v + 4.5 v.M2 v)
+  //           + k (3 M1.F - 3 M0 v.F + 9 v.M2 F).
+  float m0 = 0.f, m1[3] = {0.f, 0.f, 0.f};
+  float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const float w = weight<Q, float>(i);
-    const float ci[3] = {(float)V::cx[i], (float)V::cy[i], (float)V::cz[i]};
-    const float cv = ci[0] * c.v[0] + ci[1] * c.v[1] + ci[2] * c.v[2];
-    const float cF = ci[0] * F[0] + ci[1] * F[1] + ci[2] * F[2];
-    float feqs, S;
-    feq_and_guo(c, p.omega, p.g, i, &feqs, &S);
-    const float feq = feqs + w;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float dfeq = w * c.rho * (3.f * ci[a] + 9.f * cv * ci[a] - 3.f * c.v[a]);
-      const float dS = k * w * (-3.f * F[a] + 9.f * ci[a] * cF);
-      G[a] += mu[i] * (p.omega * dfeq + dS);
-    }
-    E += mu[i] * (p.omega * feq + S);
+    const float m = weight<Q, float>(i) * mu[i];
+    const int cx = V::cx[i], cy = V::cy[i], cz = V::cz[i];
+    m0 += m;
+    if (cx) m1[0] += cx > 0 ? m : -m;
+    if (cy) m1[1] += cy > 0 ? m : -m;
+    if (cz) m1[2] += cz > 0 ? m : -m;
+    if (cx) mxx += m;
+    if (cy) myy += m;
+    if (cz) mzz += m;
+    if (cx && cy) mxy += cx * cy > 0 ? m : -m;
+    if (cx && cz) mxz += cx * cz > 0 ? m : -m;
+    if (cy && cz) myz += cy * cz > 0 ? m : -m;
   }
-  E /= c.rho;
+  const float* v = c.v;
+  const float M2v[3] = {mxx * v[0] + mxy * v[1] + mxz * v[2], mxy * v[0] + myy * v[1] + myz * v[2],
+                        mxz * v[0] + myz * v[1] + mzz * v[2]};
+  const float M2F[3] = {mxx * F[0] + mxy * F[1] + mxz * F[2], mxy * F[0] + myy * F[1] + myz * F[2],
+                        mxz * F[0] + myz * F[1] + mzz * F[2]};
+  float G[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    G[a] = p.omega * c.rho * (3.f * m1[a] + 9.f * M2v[a] - 3.f * m0 * v[a]) +
+           k * (9.f * M2F[a] - 3.f * m0 * F[a]);
+  const float vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const float vF = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
+  const float m1v = m1[0] * v[0] + m1[1] * v[1] + m1[2] * v[2];
+  const float m1F = m1[0] * F[0] + m1[1] * F[1] + m1[2] * F[2];
+  const float vM2v = v[0] * M2v[0] + v[1] * M2v[1] + v[2] * M2v[2];
+  const float vM2F = v[0] * M2F[0] + v[1] * M2F[1] + v[2] * M2F[2];
+  const float E = p.omega * (m0 * (1.f - 1.5f * vv) + 3.f * m1v + 4.5f * vM2v) +
+                  k * (3.f * m1F - 3.f * m0 * vF + 9.f * vM2F) / c.rho;
   grad[idx] += G[0] * c.u[0] + G[1] * c.u[1] + G[2] * c.u[2];
   const float Arho = E - d * (G[0] * c.j[0] + G[1] * c.j[1] + G[2] * c.j[2]) / (c.rho * c.rho);
   const float s = d / c.rho;
