@@ -61,6 +61,34 @@ def test_required_bytes(lib):
     assert lib.lbm_required_bytes(1, 1024, 1024, 1024, 1, ctypes.byref(p), None) == _lib.ERR_UNSUPPORTED
 
 
+def test_required_bytes_follows_the_documented_placement(lib):
+    """pop_bytes for seeded shapes against the rule stated in include/lbm.h:
+    blocked (N rounded up to chunks of B = 32768 / s cells) when N > B and that
+    stays below 2^32 bytes, else q arrays of N rounded up to 64; both rounded
+    up to 256 bytes."""
+    rng = np.random.default_rng(2307)
+    size = {_lib.STORE_F64: 8, _lib.STORE_F32: 4, _lib.STORE_F16: 2, _lib.STORE_BF16: 2}
+    p = ctypes.c_size_t()
+    for _ in range(400):
+        d = int(rng.integers(0, 2))
+        q = 9 if d == 0 else 19
+        st = int(rng.integers(0, 4))
+        s = size[st]
+        scale = float(rng.choice([1e1, 1e2, 1e3, 8e3]))
+        nx, ny = (int(v) for v in rng.integers(1, scale, 2))
+        nz = 1 if d == 0 else int(rng.integers(1, scale))
+        N = nx * ny * nz
+        if q * (-(-N // 64)) * 64 >= 2**32:
+            assert lib.lbm_required_bytes(d, nx, ny, nz, st, ctypes.byref(p), None) == \
+                _lib.ERR_UNSUPPORTED
+            continue
+        assert lib.lbm_required_bytes(d, nx, ny, nz, st, ctypes.byref(p), None) == 0
+        B = 32768 // s
+        blocked = q * (-(-N // B)) * B * s
+        nbytes = blocked if (N > B and blocked < 2**32) else q * (-(-N // 64)) * 64 * s
+        assert p.value == -(-nbytes // 256) * 256, (d, nx, ny, nz, st)
+
+
 def _create(lib, d=1, n=(8, 8, 8), tau=0.8, storage=1, flags=0, pop=256, pop_b=10**9, aux=512,
             aux_b=10**9):
     h = ctypes.c_void_p()
