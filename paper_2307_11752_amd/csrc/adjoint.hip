@@ -132,11 +132,38 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int i = 0; i < Q; ++i) f[i] = src[(uint32_t)i * PS + idx];
   const CellState c = cell_state(f, por[idx], p.g);
+  // feq_and_guo by opposite pairs (i, i + H): the shifted equilibrium is
+  // P + M and P - M, P = w (drho - 1.5 rho v.v + 4.5 rho (c.v)^2) and
+  // M = 3 w rho c.v; the Guo term is GP + GM and GP - GM, GP = k w (9 (c.v)(c.F)
+  // - 3 v.F) and GM = 3 k w c.F.  The weight multiplies last (a folded
+  // constant such as 3 w would bias the momentum by its own rounding).
+  constexpr int H = (Q - 1) / 2;
+  static_assert(pairs_are_opposite<Q>(), "velocity i + H must be the opposite of velocity i");
+  const float k = 1.f - 0.5f * p.omega;
+  const float F[3] = {c.rho * p.g[0], c.rho * p.g[1], c.rho * p.g[2]};
+  const float vF = c.v[0] * F[0] + c.v[1] * F[1] + c.v[2] * F[2];
+  const float A = c.drho - 1.5f * c.rho * (c.v[0] * c.v[0] + c.v[1] * c.v[1] + c.v[2] * c.v[2]);
+  float out[Q];
+  {
+    const float w = weight<Q, float>(0);
+    out[0] = fmaf(p.omega, w * A - f[0], f[0]) + k * w * (-3.f * vF);
+  }
+#pragma unroll
+  for (int i = 1; i <= H; ++i) {
+    const float w = weight<Q, float>(i);
+    const float cv = (float)V::cx[i] * c.v[0] + (float)V::cy[i] * c.v[1] + (float)V::cz[i] * c.v[2];
+    const float cF = (float)V::cx[i] * F[0] + (float)V::cy[i] * F[1] + (float)V::cz[i] * F[2];
+    const float rc = c.rho * cv;
+    const float P = w * fmaf(4.5f * rc, cv, A);
+    const float M = w * (3.f * rc);
+    const float GP = k * w * fmaf(9.f * cv, cF, -3.f * vF);
+    const float GM = k * w * (3.f * cF);
+    out[i] = fmaf(p.omega, (P + M) - f[i], f[i]) + (GP + GM);
+    out[i + H] = fmaf(p.omega, (P - M) - f[i + H], f[i + H]) + (GP - GM);
+  }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    float feqs, S;
-    feq_and_guo(c, p.omega, p.g, i, &feqs, &S);
-    const float v = f[i] + p.omega * (feqs - f[i]) + S;
+    const float v = out[i];
     const bool wall = i > 0 && ((lw >> (i - 1)) & 1u);
     const uint32_t off = wall ? (uint32_t)V::opp[i] * PS + idx
                               : (uint32_t)i * PS + nb.at(V::cx[i], V::cy[i], V::cz[i]);
