@@ -21,7 +21,11 @@
  * --------------------------------
  *  * Every call returns an lbm_status (0 = LBM_OK, negative = error).  No call
  *    throws or aborts; on error the handle keeps its previous state and
- *    lbm_last_error() describes the failure.
+ *    lbm_last_error() describes the failure.  One exception: a HIP failure
+ *    inside lbm_step (lbm_batch_step) may leave some of the requested steps
+ *    queued, so the lattice (every member of the batch) is then marked
+ *    inconsistent: stepping and reading it return LBM_ERR_STATE until
+ *    lbm_init_equilibrium or lbm_set_populations is called again.
  *  * Cell index idx = x + nx*(y + ny*z), x fastest; N = nx*ny*nz.  D2Q9 needs nz == 1.
  *  * Device buffers are caller-owned (e.g. PyTorch tensors) and must outlive the
  *    handle.  The library never allocates device memory.
@@ -84,8 +88,9 @@ typedef enum {
  * buffer holds one array per population: element i * PS + idx, with PS = N
  * rounded up to a multiple of 64.  The value stored depends on the
  * propagation phase, so read populations with lbm_get_populations.
- * aux_bytes: per-cell link masks plus reduction scratch.  Host-only; needs no
- * GPU. */
+ * aux_bytes: per-cell link masks plus device scratch (the partial sums of
+ * lbm_totals and the staging of lbm_moments: 32 bytes per cell, at least
+ * 64 KiB and at most 1 MiB).  Host-only; needs no GPU. */
 lbm_status lbm_required_bytes(lbm_descriptor d, int nx, int ny, int nz, lbm_storage s,
                               size_t* pop_bytes, size_t* aux_bytes);
 
@@ -157,11 +162,18 @@ lbm_status lbm_step(lbm_lattice* h, int n);
  * launches (same kernels, same arguments). */
 lbm_status lbm_set_graph_steps(lbm_lattice* h, int steps);
 
-/* Macroscopic fields of the current state into device buffers: rho_dev
- * double[N] and u_dev double[3*N] (either may be NULL).  u is the
- * force-shifted velocity j/rho + g/2 of the guide's Guo velocity shift.
- * Non-fluid cells report 0.  Sums are accumulated in double.  async. */
-lbm_status lbm_moments(lbm_lattice* h, double* rho_dev, double* u_dev);
+/* Macroscopic fields of the current state (the guide's lesson "Extract Data
+ * From a Simulation"): density rho and the force-shifted velocity
+ * u = j/rho + g/2 of the guide's Guo velocity shift, decoded and accumulated
+ * in double.  Non-fluid cells report 0.
+ * lbm_moments: host buffers rho double[N] and u double[3*N] (component a of
+ * cell idx at a*N + idx); either may be NULL.  sync: the cells are decoded in
+ * chunks through the lattice's device scratch and copied to the host.
+ * lbm_moments_device: device buffers rho_dev float[N] and u_dev float[3*N]
+ * (same layout, values rounded to float once at the end); either may be
+ * NULL.  async. */
+lbm_status lbm_moments(lbm_lattice* h, double* rho, double* u);
+lbm_status lbm_moments_device(lbm_lattice* h, float* rho_dev, float* u_dev);
 
 /* Totals over fluid cells, reduced on the device in double: mass = sum rho,
  * momentum = sum_i c_i f_i (unshifted), stats = {average rho, average energy
@@ -273,8 +285,15 @@ lbm_status lbm_porous_create(lbm_porous** out, int nx, int ny, int nz, double ta
 lbm_status lbm_porous_forward(lbm_porous* h, const float* porosity_dev, double* J);
 
 /* dJ/dd for the porosity of the last forward run into grad_dev (device
- * float[N]; zero on non-fluid cells).  sync. */
+ * float[N]; zero on non-fluid cells).  sync.  LBM_ERR_STATE before any
+ * successful forward run (or after a failed one, whose checkpoints are
+ * incomplete). */
 lbm_status lbm_porous_backward(lbm_porous* h, float* grad_dev);
+
+/* Number of forward runs completed on h (0 before the first).  A caller that
+ * keeps the value of a run can tell whether lbm_porous_backward still
+ * differentiates that run: it does while the count is unchanged.  Host-only. */
+lbm_status lbm_porous_generation(const lbm_porous* h, long long* generation);
 
 /* Final populations of the last forward run, device double[19*N], natural
  * layout (f_i of cell idx at i*N + idx).  sync. */

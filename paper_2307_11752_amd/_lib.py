@@ -55,6 +55,7 @@ SIGNATURES = {
     "lbm_step": ([_P, _I], _I),
     "lbm_set_graph_steps": ([_P, _I], _I),
     "lbm_moments": ([_P, _P, _P], _I),
+    "lbm_moments_device": ([_P, _P, _P], _I),
     "lbm_totals": ([_P, _P, _P, _P], _I),
     "lbm_get_info": ([_P, _PLL, _PLL], _I),
     "lbm_lattice_destroy": ([_P], _I),
@@ -75,6 +76,7 @@ SIGNATURES = {
     "lbm_porous_forward": ([_P, _P, _PD], _I),
     "lbm_porous_backward": ([_P, _P], _I),
     "lbm_porous_get_final": ([_P, _P], _I),
+    "lbm_porous_generation": ([_P, _PLL], _I),
     "lbm_porous_destroy": ([_P], _I),
     "lbm_porous_last_error": ([_P], ctypes.c_char_p),
 }

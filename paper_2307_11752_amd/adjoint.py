@@ -65,6 +65,12 @@ class PorousChannel:
                                                   ctypes.byref(J)))
         return J.value
 
+    def generation(self):
+        """Number of forward runs completed (lbm_porous_generation)."""
+        g = ctypes.c_longlong()
+        self._chk(self.lib.lbm_porous_generation(self.h, ctypes.byref(g)))
+        return g.value
+
     def backward(self):
         """dJ/dd of the last forward run, float32 tensor (nz, ny, nx)."""
         grad = torch.empty(self.shape_zyx, dtype=torch.float32, device=self.device)
@@ -91,17 +97,29 @@ class PorousChannel:
 
 
 class PorousObjective(torch.autograd.Function):
-    """J(d) with dJ/dd from the adjoint sweep (checkpointed recomputation)."""
+    """J(d) with dJ/dd from the adjoint sweep (checkpointed recomputation).
+
+    The handle keeps the checkpoints of its latest forward run only.  Each
+    node records the porosity it was evaluated at and the handle's forward
+    count; if another forward ran on the same handle in between (a line
+    search, a finite-difference probe), backward first repeats this node's
+    forward run, so the gradient always belongs to this node's porosity."""
 
     @staticmethod
     def forward(ctx, porosity, problem):
         ctx.problem = problem
-        J = problem.forward(porosity)
+        d = porosity.detach().to(dtype=torch.float32).contiguous().clone()
+        J = problem.forward(d)
+        ctx.porosity = d
+        ctx.generation = problem.generation()
         return torch.tensor(J, dtype=torch.float64, device=porosity.device)
 
     @staticmethod
     def backward(ctx, grad_out):
-        grad = ctx.problem.backward()
+        problem = ctx.problem
+        if problem.generation() != ctx.generation:
+            problem.forward(ctx.porosity)
+        grad = problem.backward()
         return grad * grad_out.to(grad.dtype), None
 
 

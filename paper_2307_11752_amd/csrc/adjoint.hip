@@ -347,6 +347,7 @@ struct lbm_porous {
   int device = 0;
   bool have_forward = false;
   int final_buf = 0;  // 0: fa, 1: fb holds f^T
+  long long generation = 0;  // forward runs completed
   double J = 0.0;
   std::string err;
 };
@@ -481,6 +482,8 @@ lbm_status lbm_porous_forward(lbm_porous* h, const float* porosity_dev, double* 
   h->err.clear();
   if (!porosity_dev || !J) return pfail(h, LBM_ERR_ARG, "NULL argument");
   PHIP_TRY(h, hipSetDevice(h->device));
+  // the checkpoints of an earlier run are overwritten from here on
+  h->have_forward = false;
   PHIP_TRY(h, hipMemcpyAsync(h->work + h->lay.por, porosity_dev, sizeof(float) * h->N,
                              hipMemcpyDeviceToDevice, h->stream));
   float* bufs[2] = {fptr(h, h->lay.fa), fptr(h, h->lay.fb)};
@@ -504,6 +507,7 @@ lbm_status lbm_porous_forward(lbm_porous* h, const float* porosity_dev, double* 
   PHIP_TRY(h, hipStreamSynchronize(h->stream));
   h->final_buf = cur;
   h->have_forward = true;
+  ++h->generation;
   h->J = r[0];
   *J = r[0];
   if (!std::isfinite(r[0])) return pfail(h, LBM_ERR_NONFINITE, "non-finite objective");
@@ -570,6 +574,12 @@ lbm_status lbm_porous_get_final(lbm_porous* h, double* f_dev) {
   PHIP_TRY(h, hipMemcpyAsync(f_dev, dense.data(), sizeof(double) * dense.size(),
                              hipMemcpyHostToDevice, h->stream));
   PHIP_TRY(h, hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_porous_generation(const lbm_porous* h, long long* generation) {
+  if (!h || !generation) return LBM_ERR_ARG;
+  *generation = h->generation;
   return LBM_OK;
 }
 

@@ -137,8 +137,9 @@ const int THREAD_CHOICES[] = {128, 256, 512};
 const int BLOCKS_PER_CU_CHOICES[] = {0, 2, 4, 8, 16};
 
 struct BatchLayout {
-  std::vector<size_t> pop_off, aux_off;  // bytes, per lattice
-  size_t pop_total = 0, items0_off = 0, items1_off = 0, aux_total = 0;
+  std::vector<size_t> pop_off, aux_off, aux_size;  // bytes, per lattice
+  size_t pop_total = 0, items0_off = 0, items1_off = 0, scratch_off = 0, scratch_bytes = 0,
+         aux_total = 0;
   size_t max_items0 = 0, max_items1 = 0;
 };
 
@@ -150,19 +151,24 @@ lbm_status batch_layout(lbm_descriptor d, int count, const int* dims, lbm_storag
   }
   L->pop_off.resize(count);
   L->aux_off.resize(count);
-  size_t pop = 0, aux = 0, items0 = 0, items1 = 0;
+  L->aux_size.resize(count);
+  size_t pop = 0, aux = 0, items0 = 0, items1 = 0, max_cells = 0;
   for (int b = 0; b < count; ++b) {
-    size_t pb = 0, ab = 0;
-    lbm_status st = lbm_required_bytes(d, dims[3 * b], dims[3 * b + 1], dims[3 * b + 2], s, &pb, &ab);
+    size_t pb = 0;
+    lbm_status st = lbm_required_bytes(d, dims[3 * b], dims[3 * b + 1], dims[3 * b + 2], s, &pb, nullptr);
     if (st) {
       *why = "lattice " + std::to_string(b) + ": " + lbm_last_error(nullptr);
       return st;
     }
+    const size_t N = (size_t)dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
+    // a member's aux holds no scratch of its own: the members share one
+    const size_t ab = aux_layout(N, 0).total;
     L->pop_off[b] = pop;
     L->aux_off[b] = aux;
+    L->aux_size[b] = ab;
     pop += pb;  // each part is a multiple of 256 bytes
     aux += ab;
-    const size_t N = (size_t)dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
+    max_cells = std::max(max_cells, N);
     const int lanes = dims[3 * b] / row_lane_cells(dims[3 * b], storage_bytes(s));
     if (lanes > MAX_THREADS) {
       *why = "lattice " + std::to_string(b) + ": an x-row needs " + std::to_string(lanes) +
@@ -181,7 +187,9 @@ lbm_status batch_layout(lbm_descriptor d, int count, const int* dims, lbm_storag
   L->items1_off = align256(L->items0_off + sizeof(BatchItem) * items0);
   L->max_items0 = items0;
   L->max_items1 = items1;
-  L->aux_total = align256(L->items1_off + sizeof(BatchItem) * items1);
+  L->scratch_off = align256(L->items1_off + sizeof(BatchItem) * items1);
+  L->scratch_bytes = scratch_size(max_cells);
+  L->aux_total = align256(L->scratch_off + L->scratch_bytes);
   return LBM_OK;
 }
 
@@ -221,6 +229,8 @@ lbm_status bfail(lbm_batch* b, lbm_status st, const std::string& msg) {
 
 void drop_batch_graph(lbm_batch* b) {
   if (b->graph) {
+    // a replay may still be running on the batch's stream
+    (void)hipStreamSynchronize(b->stream);
     (void)hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
   }
@@ -288,6 +298,10 @@ lbm_status common_phase(lbm_batch* b, int* phase) {
     const lbm_lattice* v = b->views[l];
     if (!v->initialized)
       return bfail(b, LBM_ERR_STATE, "lattice " + std::to_string(l) + " is not initialised");
+    if (!v->consistent)
+      return bfail(b, LBM_ERR_STATE, "lattice " + std::to_string(l) +
+                                         ": a HIP failure interrupted an earlier step; initialise "
+                                         "the populations again");
     if (v->phase != b->views[0]->phase)
       return bfail(b, LBM_ERR_STATE, "lattices are in different propagation phases");
   }
@@ -300,6 +314,44 @@ void advance_views(lbm_batch* b, int n) {
     v->phase ^= (n & 1);
     v->steps += n;
   }
+}
+
+// Enqueue n steps of every member from propagation phase `phase` (graph
+// replays where set up).  Returns LBM_ERR_HIP on a HIP failure.
+lbm_status enqueue_batch_steps(lbm_batch* b, int n, int phase) {
+  int left = n;
+  if (b->graph_steps > 0 && n >= b->graph_steps) {
+    if (phase != 0) {
+      launch_one(b, 1);
+      phase = 0;
+      --left;
+    }
+    if (!b->graph && left >= b->graph_steps) {
+      hipGraph_t g = nullptr;
+      BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      for (int s = 0; s < b->graph_steps; ++s) launch_one(b, s & 1);
+      hipError_t e = hipStreamEndCapture(b->stream, &g);
+      if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return bfail(b, LBM_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      }
+      e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        b->graph = nullptr;
+        return bfail(b, LBM_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      }
+    }
+    while (b->graph && left >= b->graph_steps) {
+      BHIP_TRY(b, hipGraphLaunch(b->graph, b->stream));
+      left -= b->graph_steps;
+    }
+  }
+  for (int s = 0; s < left; ++s) {
+    launch_one(b, phase);
+    phase ^= 1;
+  }
+  return LBM_OK;
 }
 
 }  // namespace
@@ -359,10 +411,11 @@ lbm_status lbm_batch_create(lbm_batch** out, lbm_descriptor d, int count, const 
   for (int l = 0; l < count; ++l) {
     const int nx = dims[3 * l], ny = dims[3 * l + 1], nz = dims[3 * l + 2];
     lbm_lattice* v = nullptr;
-    size_t pb = 0, ab = 0;
-    lbm_required_bytes(d, nx, ny, nz, s, &pb, &ab);
-    st = lbm_lattice_create(&v, d, nx, ny, nz, tau[l], s, flags, b->pop + L.pop_off[l], pb,
-                            b->aux + L.aux_off[l], ab, hip_stream);
+    size_t pb = 0;
+    lbm_required_bytes(d, nx, ny, nz, s, &pb, nullptr);
+    st = lbm_detail::create_lattice(&v, d, nx, ny, nz, tau[l], s, flags, b->pop + L.pop_off[l], pb,
+                                    b->aux + L.aux_off[l], L.aux_size[l], hip_stream, 0,
+                                    b->aux + L.scratch_off, L.scratch_bytes);
     if (st) return undo(st, "lattice " + std::to_string(l) + ": " + lbm_last_error(nullptr));
     b->views.push_back(v);
     mat.assign((size_t)nx * ny * nz, 1);  // fully fluid, periodic on every axis
@@ -419,41 +472,20 @@ lbm_status lbm_batch_step(lbm_batch* b, int n) {
   int phase = 0;
   st = common_phase(b, &phase);
   if (st) return st;
-  int left = n;
-  if (b->graph_steps > 0 && n >= b->graph_steps) {
-    if (phase != 0) {
-      launch_one(b, 1);
-      phase = 0;
-      --left;
-    }
-    if (!b->graph && left >= b->graph_steps) {
-      hipGraph_t g = nullptr;
-      BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-      for (int s = 0; s < b->graph_steps; ++s) launch_one(b, s & 1);
-      hipError_t e = hipStreamEndCapture(b->stream, &g);
-      if (e != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return bfail(b, LBM_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-      }
-      e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (e != hipSuccess) {
-        b->graph = nullptr;
-        return bfail(b, LBM_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-      }
-    }
-    while (b->graph && left >= b->graph_steps) {
-      BHIP_TRY(b, hipGraphLaunch(b->graph, b->stream));
-      left -= b->graph_steps;
-    }
+  st = enqueue_batch_steps(b, n, phase);
+  if (st == LBM_OK) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+      st = bfail(b, LBM_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   }
-  for (int s = 0; s < left; ++s) {
-    launch_one(b, phase);
-    phase ^= 1;
+  if (st != LBM_OK) {
+    // some launches may already be queued: the members' phase and step counts
+    // no longer describe the device state
+    for (lbm_lattice* v : b->views) v->consistent = false;
+    drop_batch_graph(b);
+    return st;
   }
   advance_views(b, n);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return bfail(b, LBM_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return LBM_OK;
 }
 

@@ -18,17 +18,31 @@ constexpr int RED_FIELDS = 8;  // mass, jx, jy, jz, sum|u|^2, max|u|, fluid coun
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Device scratch of a lattice: the per-block partial totals of lbm_totals, or
+// one chunk of the moments staged for lbm_moments (4 doubles per cell).  A
+// lattice's own scratch sits in its aux buffer; the members of a batch share
+// one scratch area of the batch's aux buffer.
+constexpr size_t SCRATCH_MIN = sizeof(double) * RED_BLOCKS * RED_FIELDS;  // 64 KiB
+constexpr size_t SCRATCH_MAX = (size_t)1 << 20;                           // 1 MiB
+constexpr size_t MOMENT_BYTES_PER_CELL = 4 * sizeof(double);
+inline size_t scratch_size(size_t N) {
+  const size_t b = MOMENT_BYTES_PER_CELL * N;
+  return align256(b < SCRATCH_MIN ? SCRATCH_MIN : (b > SCRATCH_MAX ? SCRATCH_MAX : b));
+}
+
 struct AuxLayout {
-  size_t link, mov, partials, result, total;
+  size_t link, mov, result, scratch, total;
 };
 
-inline AuxLayout aux_layout(size_t N) {
+// Aux buffer of a lattice of N cells with `scratch` bytes of its own scratch
+// (0 for a batch member, which uses the batch's).
+inline AuxLayout aux_layout(size_t N, size_t scratch) {
   AuxLayout a;
   a.link = 0;
   a.mov = align256(a.link + 4 * N);
-  a.partials = align256(a.mov + 4 * N);
-  a.result = align256(a.partials + sizeof(double) * RED_BLOCKS * RED_FIELDS);
-  a.total = align256(a.result + sizeof(double) * RED_FIELDS);
+  a.result = align256(a.mov + 4 * N);
+  a.scratch = align256(a.result + sizeof(double) * RED_FIELDS);
+  a.total = align256(a.scratch + scratch);
   return a;
 }
 
@@ -90,6 +104,12 @@ struct lbm_lattice {
   unsigned char* aux = nullptr;
   size_t aux_bytes = 0;
   AuxLayout lay{};
+  unsigned char* scratch = nullptr;  // device scratch (see scratch_size)
+  size_t scratch_bytes = 0;
+  // False after a HIP failure while steps were being enqueued: the device state
+  // no longer matches phase / steps, so stepping and reading are refused until
+  // the populations are initialised again.
+  bool consistent = true;
   hipStream_t stream = nullptr;
   int device = 0;
   bool has_geometry = false, initialized = false, all_fluid = false, has_moving_cells = false;
@@ -114,6 +134,13 @@ struct lbm_lattice {
 namespace lbm_detail {
 lbm_status fail(lbm_lattice* h, lbm_status st, const std::string& msg);
 void drop_graph(lbm_lattice* h);
+// lbm_lattice_create with an explicit scratch area: own_scratch bytes of the
+// aux buffer (lbm_lattice_create uses scratch_size(N)), or, with
+// own_scratch == 0, the caller's shared scratch of shared_bytes.
+lbm_status create_lattice(lbm_lattice** out, lbm_descriptor d, int nx, int ny, int nz,
+                          double tau, lbm_storage s, unsigned flags, void* dev_pop,
+                          size_t pop_bytes, void* dev_aux, size_t aux_bytes, void* hip_stream,
+                          size_t own_scratch, unsigned char* shared, size_t shared_bytes);
 }  // namespace lbm_detail
 
 #define HIP_TRY(h, call)                                                                  \

@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbm {
 
 // ---------------------------------------------------------------------------
@@ -236,39 +238,95 @@ __device__ __forceinline__ double reciprocal(double v) { return 1.0 / v; }
 // G_P + G_M and G_P - G_M, G_P = (1 - omega/2) w_i (9 (c_i.u)(c_i.F) - 3 u.F)
 // and G_M = 3 (1 - omega/2) w_i c_i.F.  The relaxation keeps the form
 // f + omega (feq - f), whose rounding is that of the small non-equilibrium part.
+// Compile-time loop: f(integral_constant<int, K>) for K = B .. E-1, so that
+// the velocity components are constants inside the body.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// a x + b y + c z for a lattice velocity (a, b, c), components in {-1, 0, 1}.
+// Zero components contribute no instruction (a product with 0 cannot be
+// folded away by the compiler: it must keep NaN and signed-zero semantics),
+// and unit ones only a sign.  Equal in value to the full dot product.
+template <int A, int B, int C, typename T>
+__device__ __forceinline__ T cdot(T x, T y, T z) {
+  if constexpr (A != 0) {
+    T r = A > 0 ? x : -x;
+    if constexpr (B != 0) r = B > 0 ? r + y : r - y;
+    if constexpr (C != 0) r = C > 0 ? r + z : r - z;
+    return r;
+  } else if constexpr (B != 0) {
+    T r = B > 0 ? y : -y;
+    if constexpr (C != 0) r = C > 0 ? r + z : r - z;
+    return r;
+  } else if constexpr (C != 0) {
+    return C > 0 ? z : -z;
+  } else {
+    return T(0);
+  }
+}
+
+// acc + s v for a compile-time sign s in {-1, 0, 1}; `first` marks an
+// accumulator that holds nothing yet (it then becomes s v, not 0 + s v).
+template <int Sg, typename T>
+__device__ __forceinline__ void accumulate(T& acc, bool& first, T v) {
+  if constexpr (Sg != 0) {
+    if (first)
+      acc = Sg > 0 ? v : -v;
+    else
+      acc = Sg > 0 ? acc + v : acc - v;
+    first = false;
+  }
+}
+
+// One BGK + Guo collision of a cell held in registers (in place).
+//   rho = base + sum f  (base = p.base when f stores f_i - w_i, else 0;
+//                        p.base = 1 unless the storage holds scaled values)
+//   u   = j/rho + g/2                                  (Guo velocity shift)
+//   feq_i - base*w_i = w_i (sum f + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u))
+//   f*_i = f_i + omega (feq_i - f_i) + (1 - omega/2) w_i (3 (c_i - u).F + 9 (c_i.u)(c_i.F))
+// with F = rho g.  Returns rho.
+// Evaluated by opposite pairs (i, i + H): with A = sum f - 1.5 rho u.u, the
+// equilibrium is P + M for velocity i and P - M for its opposite, P = w_i (A +
+// 4.5 rho (c_i.u)^2) and M = 3 w_i rho c_i.u; the Guo source likewise is
+// G_P + G_M and G_P - G_M, G_P = (1 - omega/2) w_i (9 (c_i.u)(c_i.F) - 3 u.F)
+// and G_M = 3 (1 - omega/2) w_i c_i.F.  The relaxation keeps the form
+// f + omega (feq - f), whose rounding is that of the small non-equilibrium part.
 template <int Q, bool SHIFT, typename T>
 __device__ __forceinline__ T collide(T (&f)[Q], const StepParams<T>& p) {
   using V = Vel<Q>;
   constexpr int H = (Q - 1) / 2;
   static_assert(pairs_are_opposite<Q>(), "velocity i + H must be the opposite of velocity i");
   T sf = f[0], jx = T(0), jy = T(0), jz = T(0);
-#pragma unroll
-  for (int k = 1; k <= H; ++k) {
+  bool fx = true, fy = true, fz = true;
+  static_for<1, H + 1>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
     const T d = f[k] - f[k + H];
     sf += f[k] + f[k + H];
-    if (V::cx[k] > 0) jx += d;
-    if (V::cx[k] < 0) jx -= d;
-    if (V::cy[k] > 0) jy += d;
-    if (V::cy[k] < 0) jy -= d;
-    if (V::cz[k] > 0) jz += d;
-    if (V::cz[k] < 0) jz -= d;
-  }
+    accumulate<V::cx[k]>(jx, fx, d);
+    accumulate<V::cy[k]>(jy, fy, d);
+    accumulate<V::cz[k]>(jz, fz, d);
+  });
   const T rho = SHIFT ? p.base + sf : sf;
   const T inv = reciprocal(rho);
-  T ux = jx * inv, uy = jy * inv, uz = jz * inv;
+  T ux = jx * inv, uy = jy * inv, uz = V::D == 3 ? jz * inv : T(0);
   if (p.has_force) {
     ux += T(0.5) * p.g[0];
     uy += T(0.5) * p.g[1];
-    uz += T(0.5) * p.g[2];
+    if (V::D == 3) uz += T(0.5) * p.g[2];
   }
-  const T uu = ux * ux + uy * uy + uz * uz;
+  const T uu = V::D == 3 ? ux * ux + uy * uy + uz * uz : ux * ux + uy * uy;
   const T A = sf - T(1.5) * rho * uu;
   const T om = p.omega;
   f[0] = fma(om, weight<Q, T>(0) * A - f[0], f[0]);
-#pragma unroll
-  for (int k = 1; k <= H; ++k) {
+  static_for<1, H + 1>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
     const T w = weight<Q, T>(k);
-    const T cu = T(V::cx[k]) * ux + T(V::cy[k]) * uy + T(V::cz[k]) * uz;
+    const T cu = cdot<V::cx[k], V::cy[k], V::cz[k]>(ux, uy, uz);
     const T rc = rho * cu;
     // w multiplies last: a folded constant such as 3 w would carry its own
     // rounding (1/6 is not a binary fraction), a bias the odd part would add
@@ -277,24 +335,24 @@ __device__ __forceinline__ T collide(T (&f)[Q], const StepParams<T>& p) {
     const T M = w * (T(3) * rc);
     f[k] = fma(om, (P + M) - f[k], f[k]);
     f[k + H] = fma(om, (P - M) - f[k + H], f[k + H]);
-  }
+  });
   // The Guo source is a block of its own behind a uniform branch, so that
   // unforced lattices skip it instead of computing and discarding it.
   if (p.has_force) {
-    const T Fx = rho * p.g[0], Fy = rho * p.g[1], Fz = rho * p.g[2];
-    const T uF = ux * Fx + uy * Fy + uz * Fz;
+    const T Fx = rho * p.g[0], Fy = rho * p.g[1], Fz = V::D == 3 ? rho * p.g[2] : T(0);
+    const T uF = V::D == 3 ? ux * Fx + uy * Fy + uz * Fz : ux * Fx + uy * Fy;
     const T kg = p.kguo;
     f[0] += kg * weight<Q, T>(0) * (T(-3) * uF);
-#pragma unroll
-    for (int k = 1; k <= H; ++k) {
+    static_for<1, H + 1>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
       const T kw = kg * weight<Q, T>(k);
-      const T cu = T(V::cx[k]) * ux + T(V::cy[k]) * uy + T(V::cz[k]) * uz;
-      const T cF = T(V::cx[k]) * Fx + T(V::cy[k]) * Fy + T(V::cz[k]) * Fz;
+      const T cu = cdot<V::cx[k], V::cy[k], V::cz[k]>(ux, uy, uz);
+      const T cF = cdot<V::cx[k], V::cy[k], V::cz[k]>(Fx, Fy, Fz);
       const T GP = kw * fma(T(9) * cu, cF, T(-3) * uF);
       const T GM = kw * (T(3) * cF);
       f[k] += GP + GM;
       f[k + H] += GP - GM;
-    }
+    });
   }
   return rho;
 }

@@ -374,15 +374,18 @@ __global__ void init_eq_kernel(S* __restrict__ pop, const uint32_t* __restrict__
   }
 }
 
-// rho and shifted u of every cell (double accumulation); zeros off the fluid.
-template <int Q, typename S, bool SHIFT>
+// rho and shifted u of cells begin .. begin+count-1 (double accumulation),
+// zeros off the fluid, written as OutT: rho_out[idx - begin] and
+// u_out[a * ustride + idx - begin] for component a.
+template <int Q, typename S, bool SHIFT, typename OutT>
 __global__ void moments_kernel(const S* __restrict__ pop, const uint32_t* __restrict__ link,
-                               double* __restrict__ rho_out, double* __restrict__ u_out, int nx,
-                               int ny, int nz, uint32_t N, PopIndex L, int phase, double gx,
-                               double gy, double gz) {
+                               OutT* __restrict__ rho_out, OutT* __restrict__ u_out, int nx,
+                               int ny, int nz, PopIndex L, int phase, double gx, double gy,
+                               double gz, uint32_t begin, uint32_t count, uint32_t ustride) {
   using V = Vel<Q>;
-  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
-       idx += gridDim.x * blockDim.x) {
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < count;
+       k += gridDim.x * blockDim.x) {
+    const uint32_t idx = begin + k;
     const uint32_t lw = link[idx];
     double rho = 0.0, u[3] = {0.0, 0.0, 0.0};
     if (lw & LINK_FLUID) {
@@ -403,11 +406,11 @@ __global__ void moments_kernel(const S* __restrict__ pop, const uint32_t* __rest
       u[1] = j[1] / rho + 0.5 * gy;
       u[2] = V::D == 3 ? j[2] / rho + 0.5 * gz : 0.0;
     }
-    if (rho_out) rho_out[idx] = rho;
+    if (rho_out) rho_out[k] = (OutT)rho;
     if (u_out) {
-      u_out[idx] = u[0];
-      u_out[(size_t)N + idx] = u[1];
-      u_out[2 * (size_t)N + idx] = u[2];
+      u_out[k] = (OutT)u[0];
+      u_out[(size_t)ustride + k] = (OutT)u[1];
+      u_out[2 * (size_t)ustride + k] = (OutT)u[2];
     }
   }
 }
@@ -515,6 +518,8 @@ lbm_status fail(lbm_lattice* h, lbm_status st, const std::string& msg) {
 
 void drop_graph(lbm_lattice* h) {
   if (h->graph) {
+    // a replay may still be running on the lattice's stream
+    (void)hipStreamSynchronize(h->stream);
     (void)hipGraphExecDestroy(h->graph);
     h->graph = nullptr;
   }
@@ -765,15 +770,23 @@ struct Ops {
                        (S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), rho, u,
                        (uint32_t)h->N, h->pix);
   }
-  static void moments(lbm_lattice* h, double* rho, double* u) {
-    hipLaunchKernelGGL((moments_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
-                       (const S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), rho, u, h->nx,
-                       h->ny, h->nz, (uint32_t)h->N, h->pix, h->phase, h->g[0], h->g[1],
-                       h->g[2]);
+  template <typename OutT>
+  static void moments(lbm_lattice* h, OutT* rho, OutT* u, uint32_t begin, uint32_t count,
+                      uint32_t ustride) {
+    hipLaunchKernelGGL((moments_kernel<Q, S, SHIFT, OutT>), dim3(blocks(count)), dim3(256), 0,
+                       h->stream, (const S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), rho,
+                       u, h->nx, h->ny, h->nz, h->pix, h->phase, h->g[0], h->g[1], h->g[2],
+                       begin, count, ustride);
   }
-  static void totals(lbm_lattice* h) {
-    double* partials = (double*)(h->aux + h->lay.partials);
-    double* result = (double*)(h->aux + h->lay.result);
+  static void moments_f64(lbm_lattice* h, double* rho, double* u, uint32_t begin, uint32_t count,
+                          uint32_t ustride) {
+    moments<double>(h, rho, u, begin, count, ustride);
+  }
+  static void moments_f32(lbm_lattice* h, float* rho, float* u, uint32_t begin, uint32_t count,
+                          uint32_t ustride) {
+    moments<float>(h, rho, u, begin, count, ustride);
+  }
+  static void totals(lbm_lattice* h, double* partials, double* result) {
     hipLaunchKernelGGL((totals_partial_kernel<Q, S, SHIFT>), dim3(RED_BLOCKS), dim3(RED_THREADS),
                        0, h->stream, (const S*)h->pop, (const uint32_t*)(h->aux + h->lay.link),
                        partials, h->nx, h->ny, h->nz, (uint32_t)h->N, h->pix, h->phase,
@@ -788,14 +801,16 @@ struct OpTable {
   void (*get_pop)(lbm_lattice*, double*);
   void (*set_pop)(lbm_lattice*, const double*);
   void (*init_eq)(lbm_lattice*, const double*, const double*);
-  void (*moments)(lbm_lattice*, double*, double*);
-  void (*totals)(lbm_lattice*);
+  void (*moments_f64)(lbm_lattice*, double*, double*, uint32_t, uint32_t, uint32_t);
+  void (*moments_f32)(lbm_lattice*, float*, float*, uint32_t, uint32_t, uint32_t);
+  void (*totals)(lbm_lattice*, double*, double*);
 };
 
 template <int Q, typename S, bool SHIFT>
 OpTable table() {
   using O = Ops<Q, S, SHIFT>;
-  return OpTable{O::step, O::get_pop, O::set_pop, O::init_eq, O::moments, O::totals};
+  return OpTable{O::step, O::get_pop, O::set_pop, O::init_eq, O::moments_f64, O::moments_f32,
+                 O::totals};
 }
 
 template <int Q, bool SHIFT>
@@ -829,6 +844,82 @@ lbm_status enter(lbm_lattice* h) {
   return LBM_OK;
 }
 
+// The populations can be stepped or decoded: initialised, and not left
+// behind by a failed step (see lbm_lattice::consistent).
+lbm_status readable(lbm_lattice* h) {
+  if (!h->initialized) return fail(h, LBM_ERR_STATE, "lattice not initialised");
+  if (!h->consistent)
+    return fail(h, LBM_ERR_STATE,
+                "a HIP failure interrupted an earlier step: initialise the populations again");
+  return LBM_OK;
+}
+
+// Reduce the totals of h through `partials` (RED_BLOCKS * RED_FIELDS doubles)
+// into `result` (RED_FIELDS doubles), copy them to the host and finish the
+// statistics.  sync.
+lbm_status reduce_totals(lbm_lattice* h, double* partials, double* result, double* mass,
+                         double momentum[3], double stats[3]) {
+  ops(h).totals(h, partials, result);
+  lbm_status st = launch_check(h);
+  if (st) return st;
+  double r[RED_FIELDS];
+  HIP_TRY(h, hipMemcpyAsync(r, result, sizeof(r), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  if (mass) *mass = r[0];
+  if (momentum)
+    for (int a = 0; a < 3; ++a) momentum[a] = r[1 + a];
+  const double nf = r[6];
+  if (stats) {
+    stats[0] = nf > 0 ? r[0] / nf : 0.0;
+    stats[1] = nf > 0 ? 0.5 * r[4] / nf : 0.0;
+    stats[2] = r[5];
+  }
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(r[k])) return fail(h, LBM_ERR_NONFINITE, "non-finite value in the totals");
+  return LBM_OK;
+}
+
+// Enqueue n steps on the lattice's stream (graph replays where set up),
+// updating the phase launch by launch.  Returns LBM_ERR_HIP on a HIP failure.
+lbm_status enqueue_steps(lbm_lattice* h, int n) {
+  const OpTable t = ops(h);
+  int left = n;
+  if (h->graph_steps > 0 && n >= h->graph_steps) {
+    // The captured run starts in phase 0 and has an even length, so it can be
+    // replayed whenever the lattice is in phase 0.
+    if (h->phase != 0) {
+      t.step(h, 1);
+      h->phase = 0;
+      --left;
+    }
+    if (!h->graph && left >= h->graph_steps) {
+      hipGraph_t g = nullptr;
+      HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      for (int s = 0; s < h->graph_steps; ++s) t.step(h, s & 1);
+      hipError_t e = hipStreamEndCapture(h->stream, &g);
+      if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(h, LBM_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      }
+      e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        h->graph = nullptr;
+        return fail(h, LBM_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      }
+    }
+    while (h->graph && left >= h->graph_steps) {
+      HIP_TRY(h, hipGraphLaunch(h->graph, h->stream));
+      left -= h->graph_steps;
+    }
+  }
+  for (int s = 0; s < left; ++s) {
+    t.step(h, h->phase);
+    h->phase ^= 1;
+  }
+  return LBM_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -847,7 +938,7 @@ lbm_status lbm_required_bytes(lbm_descriptor d, int nx, int ny, int nz, lbm_stor
     const PopIndex L = pop_index(qof(d), N, storage_bytes(s));
     *pop_bytes = align256(pop_elements(qof(d), L, N) * storage_bytes(s));
   }
-  if (aux_bytes) *aux_bytes = aux_layout(N).total;
+  if (aux_bytes) *aux_bytes = aux_layout(N, scratch_size(N)).total;
   return LBM_OK;
 }
 
@@ -870,11 +961,26 @@ lbm_status lbm_lattice_create(lbm_lattice** out, lbm_descriptor d, int nx, int n
                               double tau, lbm_storage s, unsigned flags, void* dev_pop,
                               size_t pop_bytes, void* dev_aux, size_t aux_bytes,
                               void* hip_stream) {
+  const size_t N = (nx > 0 && ny > 0 && nz > 0) ? (size_t)nx * ny * nz : 0;
+  return lbm_detail::create_lattice(out, d, nx, ny, nz, tau, s, flags, dev_pop, pop_bytes, dev_aux,
+                                    aux_bytes, hip_stream, scratch_size(N), nullptr, 0);
+}
+
+}  // extern "C"
+
+lbm_status lbm_detail::create_lattice(lbm_lattice** out, lbm_descriptor d, int nx, int ny, int nz,
+                                      double tau, lbm_storage s, unsigned flags, void* dev_pop,
+                                      size_t pop_bytes, void* dev_aux, size_t aux_bytes,
+                                      void* hip_stream, size_t own_scratch, unsigned char* shared,
+                                      size_t shared_bytes) {
   if (!out) return fail(nullptr, LBM_ERR_ARG, "out is NULL");
   *out = nullptr;
-  size_t need_pop = 0, need_aux = 0;
-  lbm_status st = lbm_required_bytes(d, nx, ny, nz, s, &need_pop, &need_aux);
+  size_t need_pop = 0;
+  lbm_status st = lbm_required_bytes(d, nx, ny, nz, s, &need_pop, nullptr);
   if (st) return st;
+  const size_t need_aux = aux_layout((size_t)nx * ny * nz, own_scratch).total;
+  if (own_scratch == 0 && (!shared || shared_bytes < SCRATCH_MIN))
+    return fail(nullptr, LBM_ERR_ARG, "a lattice without its own scratch needs a shared one");
   if (!tau_ok(tau)) return fail(nullptr, LBM_ERR_ARG, "tau must be > 0.5 (or +inf for pure streaming)");
   if (flags & ~LBM_FLAG_SHIFTED) return fail(nullptr, LBM_ERR_ARG, "unknown flags");
   if (!dev_pop || !dev_aux) return fail(nullptr, LBM_ERR_ARG, "device buffers must not be NULL");
@@ -901,7 +1007,9 @@ lbm_status lbm_lattice_create(lbm_lattice** out, lbm_descriptor d, int nx, int n
   h->pop_bytes = pop_bytes;
   h->aux = (unsigned char*)dev_aux;
   h->aux_bytes = aux_bytes;
-  h->lay = aux_layout(h->N);
+  h->lay = aux_layout(h->N, own_scratch);
+  h->scratch = own_scratch ? h->aux + h->lay.scratch : shared;
+  h->scratch_bytes = own_scratch ? own_scratch : shared_bytes;
   h->stream = (hipStream_t)hip_stream;
   h->bx = nx >= 256 ? 256 : ((nx + 63) / 64) * 64;
   h->nxb = (nx + h->bx - 1) / h->bx;
@@ -916,6 +1024,8 @@ lbm_status lbm_lattice_create(lbm_lattice** out, lbm_descriptor d, int nx, int n
   *out = h;
   return LBM_OK;
 }
+
+extern "C" {
 
 lbm_status lbm_set_geometry(lbm_lattice* h, const uint8_t* material, unsigned periodic_mask) {
   lbm_status st = enter(h);
@@ -993,6 +1103,7 @@ lbm_status lbm_init_equilibrium(lbm_lattice* h, const double* rho_dev, const dou
   h->phase = 0;
   h->steps = 0;
   h->initialized = true;
+  h->consistent = true;
   return LBM_OK;
 }
 
@@ -1007,6 +1118,7 @@ lbm_status lbm_set_populations(lbm_lattice* h, const double* f_dev) {
   h->phase = 0;
   h->steps = 0;
   h->initialized = true;
+  h->consistent = true;
   return LBM_OK;
 }
 
@@ -1014,7 +1126,8 @@ lbm_status lbm_get_populations(lbm_lattice* h, double* f_dev) {
   lbm_status st = enter(h);
   if (st) return st;
   if (!f_dev) return fail(h, LBM_ERR_ARG, "f_dev is NULL");
-  if (!h->initialized) return fail(h, LBM_ERR_STATE, "lattice not initialised");
+  st = readable(h);
+  if (st) return st;
   ops(h).get_pop(h, f_dev);
   return launch_check(h);
 }
@@ -1025,43 +1138,19 @@ lbm_status lbm_step(lbm_lattice* h, int n) {
   if (h->batch) return fail(h, LBM_ERR_STATE, "lattice belongs to a batch: use the lbm_batch_* calls");
   if (n < 0) return fail(h, LBM_ERR_ARG, "n must be >= 0");
   if (!h->initialized) return fail(h, LBM_ERR_STATE, "initialise the populations first");
-  const OpTable t = ops(h);
-  int left = n;
-  if (h->graph_steps > 0 && n >= h->graph_steps) {
-    // The captured run starts in phase 0 and has an even length, so it can be
-    // replayed whenever the lattice is in phase 0.
-    if (h->phase != 0) {
-      t.step(h, 1);
-      h->phase = 0;
-      --left;
-    }
-    if (!h->graph && left >= h->graph_steps) {
-      hipGraph_t g = nullptr;
-      HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-      for (int s = 0; s < h->graph_steps; ++s) t.step(h, s & 1);
-      hipError_t e = hipStreamEndCapture(h->stream, &g);
-      if (e != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return fail(h, LBM_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-      }
-      e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (e != hipSuccess) {
-        h->graph = nullptr;
-        return fail(h, LBM_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-      }
-    }
-    while (h->graph && left >= h->graph_steps) {
-      HIP_TRY(h, hipGraphLaunch(h->graph, h->stream));
-      left -= h->graph_steps;
-    }
-  }
-  for (int s = 0; s < left; ++s) {
-    t.step(h, h->phase);
-    h->phase ^= 1;
+  st = readable(h);
+  if (st) return st;
+  st = enqueue_steps(h, n);
+  if (st == LBM_OK) st = launch_check(h);
+  if (st != LBM_OK) {
+    // some launches may already be queued: phase and step count no longer
+    // describe the device state
+    h->consistent = false;
+    drop_graph(h);
+    return st;
   }
   h->steps += n;
-  return launch_check(h);
+  return LBM_OK;
 }
 
 lbm_status lbm_set_graph_steps(lbm_lattice* h, int steps) {
@@ -1076,37 +1165,53 @@ lbm_status lbm_set_graph_steps(lbm_lattice* h, int steps) {
   return LBM_OK;
 }
 
-lbm_status lbm_moments(lbm_lattice* h, double* rho_dev, double* u_dev) {
+lbm_status lbm_moments(lbm_lattice* h, double* rho, double* u) {
   lbm_status st = enter(h);
   if (st) return st;
-  if (!h->initialized) return fail(h, LBM_ERR_STATE, "lattice not initialised");
+  st = readable(h);
+  if (st) return st;
+  if (!rho && !u) return LBM_OK;
+  // cells are decoded in chunks into the scratch (rho, then the three u
+  // components, each `chunk` doubles) and copied out; the host waits for each
+  const OpTable t = ops(h);
+  const size_t chunk = h->scratch_bytes / MOMENT_BYTES_PER_CELL;
+  double* sr = (double*)h->scratch;
+  double* su = sr + chunk;
+  for (size_t begin = 0; begin < h->N; begin += chunk) {
+    const size_t n = h->N - begin < chunk ? h->N - begin : chunk;
+    t.moments_f64(h, rho ? sr : nullptr, u ? su : nullptr, (uint32_t)begin, (uint32_t)n,
+                  (uint32_t)chunk);
+    st = launch_check(h);
+    if (st) return st;
+    if (rho)
+      HIP_TRY(h, hipMemcpyAsync(rho + begin, sr, n * sizeof(double), hipMemcpyDeviceToHost,
+                                h->stream));
+    if (u)
+      for (int a = 0; a < 3; ++a)
+        HIP_TRY(h, hipMemcpyAsync(u + (size_t)a * h->N + begin, su + (size_t)a * chunk,
+                                  n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_moments_device(lbm_lattice* h, float* rho_dev, float* u_dev) {
+  lbm_status st = enter(h);
+  if (st) return st;
+  st = readable(h);
+  if (st) return st;
   if (!rho_dev && !u_dev) return LBM_OK;
-  ops(h).moments(h, rho_dev, u_dev);
+  ops(h).moments_f32(h, rho_dev, u_dev, 0u, (uint32_t)h->N, (uint32_t)h->N);
   return launch_check(h);
 }
 
 lbm_status lbm_totals(lbm_lattice* h, double* mass, double momentum[3], double stats[3]) {
   lbm_status st = enter(h);
   if (st) return st;
-  if (!h->initialized) return fail(h, LBM_ERR_STATE, "lattice not initialised");
-  ops(h).totals(h);
-  st = launch_check(h);
+  st = readable(h);
   if (st) return st;
-  double r[RED_FIELDS];
-  HIP_TRY(h, hipMemcpyAsync(r, h->aux + h->lay.result, sizeof(r), hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(h, hipStreamSynchronize(h->stream));
-  if (mass) *mass = r[0];
-  if (momentum)
-    for (int a = 0; a < 3; ++a) momentum[a] = r[1 + a];
-  const double nf = r[6];
-  if (stats) {
-    stats[0] = nf > 0 ? r[0] / nf : 0.0;
-    stats[1] = nf > 0 ? 0.5 * r[4] / nf : 0.0;
-    stats[2] = r[5];
-  }
-  for (int k = 0; k < 6; ++k)
-    if (!std::isfinite(r[k])) return fail(h, LBM_ERR_NONFINITE, "non-finite value in the totals");
-  return LBM_OK;
+  return reduce_totals(h, (double*)h->scratch, (double*)(h->aux + h->lay.result), mass, momentum,
+                       stats);
 }
 
 lbm_status lbm_get_info(const lbm_lattice* h, long long* steps, long long* fluid_cells) {

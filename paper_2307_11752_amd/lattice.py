@@ -192,13 +192,23 @@ class Lattice(_Handle):
         return out
 
     def moments(self):
-        """(rho (nz,ny,nx), u (3,nz,ny,nx)) float64 tensors on the GPU."""
-        rho = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
-        u = torch.empty((3, self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        """(rho (nz,ny,nx), u (3,nz,ny,nx)) as float64 numpy arrays on the host
+        (lbm_moments: decoded in double, sync)."""
+        rho = np.empty((self.nz, self.ny, self.nx), dtype=np.float64)
+        u = np.empty((3, self.nz, self.ny, self.nx), dtype=np.float64)
         with stream_order(self.stream, self.device):
-            self._chk(self.lib.lbm_moments(self.h, ctypes.c_void_p(rho.data_ptr()),
-                                           ctypes.c_void_p(u.data_ptr())))
-        self.stream.synchronize()
+            self._chk(self.lib.lbm_moments(self.h, rho.ctypes.data_as(ctypes.c_void_p),
+                                           u.ctypes.data_as(ctypes.c_void_p)))
+        return rho, u
+
+    def moments_device(self):
+        """(rho (nz,ny,nx), u (3,nz,ny,nx)) as float32 tensors on the GPU
+        (lbm_moments_device, ordered on the caller's stream)."""
+        rho = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float32, device=self.device)
+        u = torch.empty((3, self.nz, self.ny, self.nx), dtype=torch.float32, device=self.device)
+        with stream_order(self.stream, self.device):
+            self._chk(self.lib.lbm_moments_device(self.h, ctypes.c_void_p(rho.data_ptr()),
+                                                  ctypes.c_void_p(u.data_ptr())))
         return rho, u
 
     def totals(self):

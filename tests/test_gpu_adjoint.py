@@ -103,6 +103,34 @@ def test_autograd_function(adj):
     prob.close()
 
 
+def test_autograd_after_another_forward_on_the_same_handle(adj):
+    """Two objective evaluations on one handle before the first is
+    differentiated (a line search does this): each node's gradient belongs to
+    its own porosity, equal to a direct forward + backward at that porosity."""
+    mat = _channel(SHAPE, interior_walls=False)
+    prob = adj.PorousChannel(mat, 0b001, TAU, G, 30, 6)
+    d1 = torch.tensor(_smooth_porosity(SHAPE, 6), dtype=torch.float32, device="cuda",
+                      requires_grad=True)
+    d2 = torch.tensor(_smooth_porosity(SHAPE, 7, lo=0.5), dtype=torch.float32, device="cuda",
+                      requires_grad=True)
+    J1 = adj.porous_objective(d1, prob)
+    g0 = prob.generation()
+    J2 = adj.porous_objective(d2, prob)
+    assert prob.generation() == g0 + 1
+    J1.backward()  # stale: the handle last ran d2
+    J2.backward()
+    direct = adj.PorousChannel(mat, 0b001, TAU, G, 30, 6)
+    assert direct.forward(d1) == J1.item()
+    r1 = direct.backward()
+    assert direct.forward(d2) == J2.item()
+    r2 = direct.backward()
+    assert not torch.equal(r1, r2)
+    assert torch.equal(d1.grad, r1)
+    assert torch.equal(d2.grad, r2)
+    prob.close()
+    direct.close()
+
+
 def test_porous_errors(adj):
     from paper_2307_11752_amd import _lib
 

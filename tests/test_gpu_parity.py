@@ -50,6 +50,9 @@ CASES_3D = [
     # per-cell phase 1
     ((66, 33, 31), 0b011),
     ((520, 12, 11), 0b111),
+    # >= 65536 cells with walls on the x and y faces and rows of 48 cells
+    # (a multiple of every lane width): flat masked phase 0, per-cell phase 1
+    ((48, 37, 37), 0b100),
 ]
 CASES_2D = [
     ((9, 7, 1), 0b00),
@@ -203,10 +206,14 @@ def test_fp64_full_steps(orc, lbm, shifted, d, case):
         assert err <= 1e-13, err
     print(f"  max|df| = {worst:.3e}")
     # moments and totals of the final state
-    rho_g, u_g = (t.cpu().numpy() for t in gpu.moments())
+    rho_g, u_g = gpu.moments()
     rho_o, u_o = ref.moments()
     assert np.max(np.abs(rho_g - rho_o)) <= 1e-13
     assert np.max(np.abs(u_g - u_o)) <= 1e-13
+    # the device call decodes the same way and rounds once to float
+    rd, ud = gpu.moments_device()
+    assert np.array_equal(rd.cpu().numpy(), rho_g.astype(np.float32))
+    assert np.array_equal(ud.cpu().numpy(), u_g.astype(np.float32))
     m_g, j_g, s_g = gpu.totals()
     m_o, j_o, s_o = ref.totals()
     assert abs(m_g - m_o) <= 1e-12 * m_o
@@ -214,6 +221,32 @@ def test_fp64_full_steps(orc, lbm, shifted, d, case):
     # rounding differs by at most about N * eps
     np.testing.assert_allclose(j_g, j_o, rtol=0, atol=1e-15 * mat.size)
     np.testing.assert_allclose(s_g, s_o, rtol=1e-11, atol=1e-15)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_moments_span_several_scratch_chunks(orc, lbm, storage):
+    """lbm_moments decodes through a device scratch of 32768 cells per chunk:
+    a lattice of 69,120 cells takes three chunks, the last one partial."""
+    shape, periodic = (48, 40, 36), W.PERIODIC_X | W.PERIODIC_Z
+    print(f"[moments chunks] shape={shape} storage={storage}", flush=True)
+    gpu, ref, mat = _pair(orc, lbm, 1, shape, periodic, 0.7, storage, True, seed=31,
+                          g=(1e-4, 0.0, 2e-5), uw=(0.02, 0.0, 0.0))
+    rho = W.random_density(shape, 4)
+    u = W.random_velocity(shape, 5)
+    gpu.init_equilibrium(rho, u)
+    ref.init_equilibrium(rho, u)
+    gpu.step(3)
+    ref.step(3)
+    rho_g, u_g = gpu.moments()
+    rho_o, u_o = ref.moments()
+    fl = _fluid(mat)
+    bar = 1e-13 if storage == "f64" else 1e-5
+    assert np.max(np.abs(rho_g[fl] - rho_o[fl])) <= bar
+    assert np.max(np.abs(u_g[:, fl] - u_o[:, fl])) <= bar
+    assert not np.any(rho_g[~fl]) and not np.any(u_g[:, ~fl])
+    rd, ud = gpu.moments_device()
+    assert np.array_equal(rd.cpu().numpy(), rho_g.astype(np.float32))
+    assert np.array_equal(ud.cpu().numpy(), u_g.astype(np.float32))
 
 
 @pytest.mark.parametrize("shifted", [False, True])
@@ -242,6 +275,7 @@ def test_fp64_full_steps_fluid_box(orc, lbm, shifted, d, shape):
                                              ("f16", True), ("bf16", True)])
 @pytest.mark.parametrize("d,case", [(1, CASES_3D[0]), (1, CASES_3D[3]), (1, CASES_3D[4]),
                                     (1, CASES_3D[6]), (1, CASES_3D[7]), (1, CASES_3D[8]),
+                                    (1, CASES_3D[9]),
                                     (0, CASES_2D[0]), (0, CASES_2D[3]), (0, CASES_2D[4]),
                                     (1, ((64, 4, 3), "fluid")), (1, ((12, 5, 4), "fluid")),
                                     (0, ((128, 6, 1), "fluid"))])
@@ -293,6 +327,7 @@ def test_one_step_within_storage_ulp(orc, lbm, storage, shifted, d, case, parity
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("shifted", [False, True])
 @pytest.mark.parametrize("d,case", [(1, CASES_3D[2]), (1, CASES_3D[4]), (1, CASES_3D[7]),
+                                    (1, CASES_3D[6]), (1, CASES_3D[9]),
                                     (0, CASES_2D[2]), (0, CASES_2D[4]),
                                     (1, ((64, 6, 5), "fluid")), (0, ((128, 16, 1), "fluid"))])
 def test_fp32_many_steps(orc, lbm, shifted, d, case):
@@ -310,7 +345,7 @@ def test_fp32_many_steps(orc, lbm, shifted, d, case):
     gpu.step(100)
     ref.step(100)
     fl = _fluid(mat)
-    rho_g, u_g = (t.cpu().numpy() for t in gpu.moments())
+    rho_g, u_g = gpu.moments()
     rho_o, u_o = ref.moments()
     e = rel_l2(u_g[:, fl], u_o[:, fl])
     print(f"[fp32-100] d={d} shifted={shifted} u rel-L2 = {e:.3e}, "
@@ -354,8 +389,8 @@ def test_graph_replay_matches_direct_launches(orc, lbm, d, shape, periodic, stor
         a.step(n)
         b.step(n)
         torch.cuda.synchronize()
-        ra, ua = a.moments()  # eager work between replays
-        rb, ub = b.moments()
+        ra, ua = a.moments_device()  # eager work between replays
+        rb, ub = b.moments_device()
         assert torch.equal(ua, ub) and torch.equal(ra, rb)
         assert torch.equal(a.get_populations(), b.get_populations())
     # a parameter change rebuilds the graph
