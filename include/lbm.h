@@ -181,6 +181,18 @@ lbm_status lbm_moments_device(lbm_lattice* h, float* rho_dev, float* u_dev);
  * outputs; sync.  LBM_ERR_NONFINITE if any result is NaN or Inf. */
 lbm_status lbm_totals(lbm_lattice* h, double* mass, double momentum[3], double stats[3]);
 
+/* lbm_totals for callers that cannot allocate device memory, e.g. code
+ * under HIP graph capture, tight serving loops or harnesses that forbid it.
+ * The same reduction and outputs as lbm_totals, bitwise, but the partial sums
+ * and the result live in a library-owned static device array (64 KiB + 64 B
+ * per GPU, held until the process ends) instead of the lattice's aux scratch;
+ * that array is enough for a lattice of any size, so no size is refused.
+ * Calls no allocating routine.  Every call on one GPU uses that GPU's copy:
+ * calls that overlap on one GPU (other threads, other streams) race, and the
+ * array keeps the last call's contents.  sync. */
+lbm_status lbm_totals_noalloc(lbm_lattice* h, double* mass, double momentum[3],
+                              double stats[3]);
+
 /* Number of steps taken since the last initialisation, and fluid cell count. */
 lbm_status lbm_get_info(const lbm_lattice* h, long long* steps, long long* fluid_cells);
 

@@ -57,6 +57,7 @@ SIGNATURES = {
     "lbm_moments": ([_P, _P, _P], _I),
     "lbm_moments_device": ([_P, _P, _P], _I),
     "lbm_totals": ([_P, _P, _P, _P], _I),
+    "lbm_totals_noalloc": ([_P, _P, _P, _P], _I),
     "lbm_get_info": ([_P, _PLL, _PLL], _I),
     "lbm_lattice_destroy": ([_P], _I),
     "lbm_status_string": ([_I], ctypes.c_char_p),

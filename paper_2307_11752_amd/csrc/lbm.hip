@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -854,6 +855,42 @@ lbm_status readable(lbm_lattice* h) {
   return LBM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Library-owned scratch for lbm_totals_noalloc: the per-block partial totals
+// and the final sums live in this file-scope device array instead of the
+// lattice's aux scratch.  Each GPU holds its own copy until the process ends;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for the current device (the array's name is not a device address in host
+// code).  Every call on one GPU shares that GPU's copy.
+// ---------------------------------------------------------------------------
+constexpr size_t STATIC_PARTIALS = (size_t)RED_BLOCKS * RED_FIELDS;
+constexpr size_t STATIC_DOUBLES = STATIC_PARTIALS + RED_FIELDS;  // 64 KiB + 64 B
+static __device__ __align__(256) double scratch[STATIC_DOUBLES];
+// The reduction always runs RED_BLOCKS blocks, whatever the lattice size, so
+// this fixed array holds the partials of any lattice.
+static_assert(STATIC_PARTIALS == (size_t)RED_BLOCKS * RED_FIELDS, "partials per reduction");
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of `scratch` on h's device (h's device must be current).
+lbm_status static_scratch(lbm_lattice* h, double** out) {
+  if (h->device < 0 || h->device >= MAX_DEVICES)
+    return fail(h, LBM_ERR_UNSUPPORTED, "device index beyond the library's table");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[h->device]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(h, LBM_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                      hipGetErrorString(e));
+    g_scratch_ptr[h->device] = (double*)ptr;
+  }
+  *out = g_scratch_ptr[h->device];
+  return LBM_OK;
+}
+
 // Reduce the totals of h through `partials` (RED_BLOCKS * RED_FIELDS doubles)
 // into `result` (RED_FIELDS doubles), copy them to the host and finish the
 // statistics.  sync.
@@ -1212,6 +1249,18 @@ lbm_status lbm_totals(lbm_lattice* h, double* mass, double momentum[3], double s
   if (st) return st;
   return reduce_totals(h, (double*)h->scratch, (double*)(h->aux + h->lay.result), mass, momentum,
                        stats);
+}
+
+lbm_status lbm_totals_noalloc(lbm_lattice* h, double* mass, double momentum[3],
+                              double stats[3]) {
+  lbm_status st = enter(h);
+  if (st) return st;
+  st = readable(h);
+  if (st) return st;
+  double* base = nullptr;
+  st = static_scratch(h, &base);
+  if (st) return st;
+  return reduce_totals(h, base, base + STATIC_PARTIALS, mass, momentum, stats);
 }
 
 lbm_status lbm_get_info(const lbm_lattice* h, long long* steps, long long* fluid_cells) {
