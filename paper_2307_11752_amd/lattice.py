@@ -153,14 +153,20 @@ class Lattice(_Handle):
     # Inputs are staged and outputs allocated on the caller's stream; each call
     # is ordered after that work and before the caller's next (stream_order).
     def init_equilibrium(self, rho=None, u=None):
-        """rho: N values or None (1); u: (dim or 3, N...) values or None (0)."""
+        """rho: N values or None (1); u: (dim or 3, N...) values or None (0).
+        Device float64 tensors of the full shape ((N...) and (3, N...)) are
+        used in place; anything else is staged on the device first."""
         r = self._dev64(rho, self.N)
         uu = None
         if u is not None:
-            ut = torch.as_tensor(u, dtype=torch.float64).reshape(-1, self.N)
-            full = torch.zeros((3, self.N), dtype=torch.float64)
-            full[: ut.shape[0]] = ut.cpu() if ut.device.type != "cpu" else ut
-            uu = full.to(self.device)
+            ut = torch.as_tensor(u, dtype=torch.float64)
+            if ut.device == self.device and ut.numel() == 3 * self.N:
+                uu = ut.reshape(3, self.N).contiguous()
+            else:
+                ut = ut.reshape(-1, self.N)
+                full = torch.zeros((3, self.N), dtype=torch.float64, device=self.device)
+                full[: ut.shape[0]] = ut.to(self.device)
+                uu = full
         with stream_order(self.stream, self.device):
             self._chk(self.lib.lbm_init_equilibrium(
                 self.h, None if r is None else ctypes.c_void_p(r.data_ptr()),
