@@ -115,35 +115,22 @@ struct PorousParams {
   float g[3];
 };
 
-// Forward: collide every fluid cell of src with its porosity and push to dst
-// (wall links reflect into the cell's own opposite slot).
-__global__ void __launch_bounds__(256)
-    porous_step_kernel(const float* __restrict__ src, float* __restrict__ dst,
-                       const float* __restrict__ por, const uint32_t* __restrict__ link, int nx,
-                       int ny, int nz, uint32_t N, uint32_t PS, PorousParams p) {
-  const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= N) return;
-  const uint32_t lw = link[idx];
-  if (!(lw & LINK_FLUID)) return;
-  const int x = (int)(idx % (uint32_t)nx);
-  const int r = (int)(idx / (uint32_t)nx);
-  const Nbr nb = make_nbr(x, r % ny, r / ny, nx, ny, nz);
-  float f[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] = src[(uint32_t)i * PS + idx];
-  const CellState c = cell_state(f, por[idx], p.g);
-  // feq_and_guo by opposite pairs (i, i + H): the shifted equilibrium is
-  // P + M and P - M, P = w (drho - 1.5 rho v.v + 4.5 rho (c.v)^2) and
-  // M = 3 w rho c.v; the Guo term is GP + GM and GP - GM, GP = k w (9 (c.v)(c.F)
-  // - 3 v.F) and GM = 3 k w c.F.  The weight multiplies last (a folded
-  // constant such as 3 w would bias the momentum by its own rounding).
+// Porous BGK + Guo collision of one cell held in registers: f (stored values
+// f_i - w_i) and its porosity d in, the post-collision stored values out.
+// Evaluated by opposite pairs (i, i + H): the shifted equilibrium is P + M and
+// P - M, P = w (drho - 1.5 rho v.v + 4.5 rho (c.v)^2) and M = 3 w rho c.v; the
+// Guo term is GP + GM and GP - GM, GP = k w (9 (c.v)(c.F) - 3 v.F) and
+// GM = 3 k w c.F.  The weight multiplies last (a folded constant such as 3 w
+// would bias the momentum by its own rounding).
+__device__ __forceinline__ void porous_collide_cell(const float (&f)[Q], float d,
+                                                    const PorousParams& p, float (&out)[Q]) {
+  const CellState c = cell_state(f, d, p.g);
   constexpr int H = (Q - 1) / 2;
   static_assert(pairs_are_opposite<Q>(), "velocity i + H must be the opposite of velocity i");
   const float k = 1.f - 0.5f * p.omega;
   const float F[3] = {c.rho * p.g[0], c.rho * p.g[1], c.rho * p.g[2]};
   const float vF = c.v[0] * F[0] + c.v[1] * F[1] + c.v[2] * F[2];
   const float A = c.drho - 1.5f * c.rho * (c.v[0] * c.v[0] + c.v[1] * c.v[1] + c.v[2] * c.v[2]);
-  float out[Q];
   {
     const float w = weight<Q, float>(0);
     out[0] = fmaf(p.omega, w * A - f[0], f[0]) + k * w * (-3.f * vF);
@@ -161,44 +148,40 @@ __global__ void __launch_bounds__(256)
     out[i] = fmaf(p.omega, (P + M) - f[i], f[i]) + (GP + GM);
     out[i + H] = fmaf(p.omega, (P - M) - f[i + H], f[i + H]) + (GP - GM);
   }
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const float v = out[i];
-    const bool wall = i > 0 && ((lw >> (i - 1)) & 1u);
-    const uint32_t off = wall ? (uint32_t)V::opp[i] * PS + idx
-                              : (uint32_t)i * PS + nb.at(V::cx[i], V::cy[i], V::cz[i]);
-    dst[off] = v;
-  }
 }
 
-// Adjoint of one step at state f (natural layout): pull mu from lam_next,
-// write lam_cur, accumulate the porosity gradient.
+// Forward: collide every fluid cell of src with its porosity and push to dst
+// (wall links reflect into the cell's own opposite slot).  One cell per thread.
 __global__ void __launch_bounds__(256)
-    porous_adjoint_kernel(const float* __restrict__ f_t, const float* __restrict__ lam_next,
-                          float* __restrict__ lam_cur, float* __restrict__ grad,
-                          const float* __restrict__ por, const uint32_t* __restrict__ link,
-                          int nx, int ny, int nz, uint32_t N, uint32_t PS, PorousParams p) {
+    porous_step_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                       const float* __restrict__ por, const uint32_t* __restrict__ link, int nx,
+                       int ny, int nz, uint32_t N, uint32_t PS, PorousParams p) {
   const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= N) return;
   const uint32_t lw = link[idx];
-  if (!(lw & LINK_FLUID)) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) lam_cur[(uint32_t)i * PS + idx] = 0.f;
-    return;
-  }
+  if (!(lw & LINK_FLUID)) return;
   const int x = (int)(idx % (uint32_t)nx);
   const int r = (int)(idx / (uint32_t)nx);
   const Nbr nb = make_nbr(x, r % ny, r / ny, nx, ny, nz);
-  float mu[Q], f[Q];
+  float f[Q], out[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) f[i] = src[(uint32_t)i * PS + idx];
+  porous_collide_cell(f, por[idx], p, out);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const bool wall = i > 0 && ((lw >> (i - 1)) & 1u);
     const uint32_t off = wall ? (uint32_t)V::opp[i] * PS + idx
                               : (uint32_t)i * PS + nb.at(V::cx[i], V::cy[i], V::cz[i]);
-    mu[i] = lam_next[off];
-    f[i] = f_t[(uint32_t)i * PS + idx];
+    dst[off] = out[i];
   }
-  const float d = por[idx];
+}
+
+// Adjoint of one cell's collision: f (stored values at step t), mu (the
+// pulled adjoint of step t + 1) and porosity d in; lambda^t of the cell out;
+// returns the cell's contribution G.u to dJ/dd.
+__device__ __forceinline__ float porous_adjoint_cell(const float (&f)[Q], const float (&mu)[Q],
+                                                     float d, const PorousParams& p,
+                                                     float (&lam)[Q]) {
   const CellState c = cell_state(f, d, p.g);
   const float k = 1.f - 0.5f * p.omega;
   const float F[3] = {c.rho * p.g[0], c.rho * p.g[1], c.rho * p.g[2]};
@@ -247,14 +230,45 @@ __global__ void __launch_bounds__(256)
   const float vM2F = v[0] * M2F[0] + v[1] * M2F[1] + v[2] * M2F[2];
   const float E = p.omega * (m0 * (1.f - 1.5f * vv) + 3.f * m1v + 4.5f * vM2v) +
                   k * (3.f * m1F - 3.f * m0 * vF + 9.f * vM2F) / c.rho;
-  grad[idx] += G[0] * c.u[0] + G[1] * c.u[1] + G[2] * c.u[2];
   const float Arho = E - d * (G[0] * c.j[0] + G[1] * c.j[1] + G[2] * c.j[2]) / (c.rho * c.rho);
   const float s = d / c.rho;
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    lam_cur[(uint32_t)i * PS + idx] = (1.f - p.omega) * mu[i] + Arho +
-                                      s * (G[0] * (float)V::cx[i] + G[1] * (float)V::cy[i] +
-                                           G[2] * (float)V::cz[i]);
+    lam[i] = (1.f - p.omega) * mu[i] + Arho +
+             s * (G[0] * (float)V::cx[i] + G[1] * (float)V::cy[i] + G[2] * (float)V::cz[i]);
+  return G[0] * c.u[0] + G[1] * c.u[1] + G[2] * c.u[2];
+}
+
+// Adjoint of one step at state f (natural layout): pull mu from lam_next,
+// write lam_cur, accumulate the porosity gradient.  One cell per thread.
+__global__ void __launch_bounds__(256)
+    porous_adjoint_kernel(const float* __restrict__ f_t, const float* __restrict__ lam_next,
+                          float* __restrict__ lam_cur, float* __restrict__ grad,
+                          const float* __restrict__ por, const uint32_t* __restrict__ link,
+                          int nx, int ny, int nz, uint32_t N, uint32_t PS, PorousParams p) {
+  const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N) return;
+  const uint32_t lw = link[idx];
+  if (!(lw & LINK_FLUID)) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lam_cur[(uint32_t)i * PS + idx] = 0.f;
+    return;
+  }
+  const int x = (int)(idx % (uint32_t)nx);
+  const int r = (int)(idx / (uint32_t)nx);
+  const Nbr nb = make_nbr(x, r % ny, r / ny, nx, ny, nz);
+  float mu[Q], f[Q], lam[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const bool wall = i > 0 && ((lw >> (i - 1)) & 1u);
+    const uint32_t off = wall ? (uint32_t)V::opp[i] * PS + idx
+                              : (uint32_t)i * PS + nb.at(V::cx[i], V::cy[i], V::cz[i]);
+    mu[i] = lam_next[off];
+    f[i] = f_t[(uint32_t)i * PS + idx];
+  }
+  grad[idx] += porous_adjoint_cell(f, mu, por[idx], p, lam);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) lam_cur[(uint32_t)i * PS + idx] = lam[i];
 }
 
 // Rest state (rho = 1, u = 0: f_i = w_i), stored shifted: zero everywhere.
@@ -377,10 +391,20 @@ float* fptr(lbm_porous* h, size_t off) { return (float*)(h->work + off); }
 constexpr unsigned POROUS_THREADS = 128;
 
 void launch_step(lbm_porous* h, const float* src, float* dst) {
+  const uint32_t* link = (const uint32_t*)(h->work + h->lay.link);
+  const float* por = fptr(h, h->lay.por);
   hipLaunchKernelGGL(porous_step_kernel, dim3(grid_for(h->N, POROUS_THREADS)),
-                     dim3(POROUS_THREADS), 0, h->stream, src, dst,
-                     fptr(h, h->lay.por), (const uint32_t*)(h->work + h->lay.link), h->nx, h->ny,
+                     dim3(POROUS_THREADS), 0, h->stream, src, dst, por, link, h->nx, h->ny,
                      h->nz, (uint32_t)h->N, (uint32_t)h->PS, h->p);
+}
+
+void launch_adjoint(lbm_porous* h, const float* f_t, const float* lam_next, float* lam_cur,
+                    float* grad) {
+  const uint32_t* link = (const uint32_t*)(h->work + h->lay.link);
+  const float* por = fptr(h, h->lay.por);
+  hipLaunchKernelGGL(porous_adjoint_kernel, dim3(grid_for(h->N, POROUS_THREADS)),
+                     dim3(POROUS_THREADS), 0, h->stream, f_t, lam_next, lam_cur, grad, por, link,
+                     h->nx, h->ny, h->nz, (uint32_t)h->N, (uint32_t)h->PS, h->p);
 }
 
 lbm_status check_args(int nx, int ny, int nz, int steps, int every, std::string* why) {
@@ -530,7 +554,6 @@ lbm_status lbm_porous_backward(lbm_porous* h, float* grad_dev) {
                      0, h->stream, fT, link, lam[0], h->plane_x, h->nx, h->ny, h->nz,
                      (uint32_t)h->PS, (const double*)(h->work + h->lay.red));
   int cur = 0;  // lam[cur] holds lambda^{t+1}
-  const float* por = fptr(h, h->lay.por);
   for (int k = h->lay.nckpt - 1; k >= 0; --k) {
     const int t0 = k * h->every;
     const int t1 = std::min(t0 + h->every, h->steps);
@@ -540,10 +563,7 @@ lbm_status lbm_porous_backward(lbm_porous* h, float* grad_dev) {
                                h->lay.state_bytes, hipMemcpyDeviceToDevice, h->stream));
     for (int s = 1; s < t1 - t0; ++s) launch_step(h, seg + nstate * (s - 1), seg + nstate * s);
     for (int t = t1 - 1; t >= t0; --t) {
-      hipLaunchKernelGGL(porous_adjoint_kernel, dim3(grid_for(h->N, POROUS_THREADS)),
-                         dim3(POROUS_THREADS), 0, h->stream,
-                         seg + nstate * (size_t)(t - t0), lam[cur], lam[cur ^ 1], grad_dev, por,
-                         link, h->nx, h->ny, h->nz, (uint32_t)h->N, (uint32_t)h->PS, h->p);
+      launch_adjoint(h, seg + nstate * (size_t)(t - t0), lam[cur], lam[cur ^ 1], grad_dev);
       cur ^= 1;
     }
   }

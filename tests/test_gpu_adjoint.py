@@ -74,6 +74,36 @@ def test_forward_and_gradient_match_oracle(orc, adj):
     prob.close()
 
 
+@pytest.mark.parametrize("shape", [(8, 10, 128), (6, 8, 256)])
+def test_long_rows_forward_and_gradient_match_oracle(orc, adj, shape):
+    """Plain channels (walls on the y and z faces only, periodic x) with x-rows
+    as long as the benchmark's (128) and twice that, so that a block spans
+    less than one row; same bars as the default case."""
+    mat = _channel(shape, interior_walls=False)
+    por = _smooth_porosity(shape, 11)
+    steps = 40
+    ref = orc.PorousProblem(1, mat, 0b001, TAU, G)
+    J_o, grad_o = ref.gradient(por, steps)
+    _, fT_o = ref.forward(por, steps)
+    print(f"[adjoint long rows] shape {shape}", flush=True)
+    prob = adj.PorousChannel(mat, 0b001, TAU, G, steps, 8)
+    d = torch.tensor(por, dtype=torch.float32, device="cuda")
+    J_g = prob.forward(d)
+    grad_g = prob.backward().cpu().numpy().astype(np.float64)
+    fT_g = prob.final_populations().cpu().numpy()
+    fl = mat == 1
+    ferr = float(np.max(np.abs(fT_g[:, fl] - fT_o[:, fl])))
+    gerr = float(np.linalg.norm(grad_g[fl] - grad_o[fl]) / np.linalg.norm(grad_o[fl]))
+    gmax = float(np.max(np.abs(grad_g[fl] - grad_o[fl])) / np.max(np.abs(grad_o[fl])))
+    print(f"  J rel {abs(J_g / J_o - 1):.2e}; max|df| {ferr:.2e}; grad rel-L2 {gerr:.2e}, "
+          f"rel-max {gmax:.2e}")
+    assert np.all(grad_g[~fl] == 0.0)
+    assert ferr <= 1e-9
+    assert abs(J_g / J_o - 1.0) <= 1e-6
+    assert gerr <= 2e-5 and gmax <= 1e-4
+    prob.close()
+
+
 @pytest.mark.parametrize("every", [1, 7, 60])
 def test_checkpoint_interval_does_not_change_the_gradient(adj, every):
     """Recomputation from checkpoints reproduces the stored states exactly, so
