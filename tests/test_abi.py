@@ -167,3 +167,24 @@ def test_cavity_workload_layout():
     assert np.all(m[-1, :] == 3)
     assert np.all(m[0, :] == 2) and np.all(m[:-1, 0] == 2) and np.all(m[:-1, -1] == 2)
     assert np.all(m[1:-1, 1:-1] == 1)
+
+
+def test_header_is_c_and_links(lib, tmp_path):
+    """The public header compiles as strict C99 and a C program linked against
+    the library makes the host-only calls (tests/c_abi_check.c)."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    exe = str(tmp_path / "c_abi_check")
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    cmd = [cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+           "-I", os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "c_abi_check.c"),
+           "-L", libdir, "-llbm_hip", f"-Wl,-rpath,{libdir}", "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "c abi ok" in r.stdout
