@@ -385,8 +385,8 @@ def bench_ensemble(args):
                      "traffic": measured_traffic(
                          f"ensemble/{storage}{'-shifted' if shifted else ''}", "batch"),
                      "algorithmic_bytes_per_launch": alg_bytes,
-                     "kernel": f"batch_step_kernel<Q=19,{storage}> phase 0 + phase 1, one launch "
-                               "per step alternating, averaged over both"},
+                     "kernel": f"batch_step_kernel<Q=19,{storage}> phase 0 (one launch) + phase 1 "
+                               "(one launch per lane width), alternating, averaged over both"},
         "cpu_baseline": cpu,
         "oracle_parity": parity,
         "unbatched_mlups": round(unbatched, 2),

@@ -1,7 +1,7 @@
 // batch.hip -- an ensemble of fully periodic lattices of uneven size, each with
-// its own relaxation time, advanced together: one persistent launch per time
-// step walks a work list of (lattice, cell range) items, and runs of steps
-// replay as one captured HIP graph.
+// its own relaxation time, advanced together: each time step walks a work list
+// of (lattice, cell range) items in one launch (phase 0) or one launch per
+// lane width (phase 1), and runs of steps replay as one captured HIP graph.
 //
 // The per-cell update is the same fused BGK collide-and-stream as the single
 // lattice path (OpenLB User Guide 1.6, Introduction, collision and streaming
@@ -49,10 +49,13 @@ struct BatchItem {
   uint32_t count;  // phase 0: cells; phase 1: rows
 };
 
-// One launch advances every lattice of the batch by one step.  Items never
-// span two lattices, so a block's lattice (and its lane width) is uniform and
-// the barriers of the phase-1 row body are reached by the whole block.
-template <int Q, typename S, bool SHIFT, int PHASE>
+// One launch advances every lattice of the batch through one phase; phase 1
+// takes one launch per lane width LC (cells per lane of its items' rows), so
+// each width gets the registers, and with them the occupancy, of its own row
+// body instead of the widest body's.  Items never span two lattices, so a
+// block's lattice is uniform and the barriers of the phase-1 row body are
+// reached by the whole block.
+template <int Q, typename S, bool SHIFT, int PHASE, int LC>
 __global__ void __launch_bounds__(512)
     batch_step_kernel(S* __restrict__ base, const BatchItem* __restrict__ items, int nitems) {
   using T = typename Store<S>::T;
@@ -78,32 +81,35 @@ __global__ void __launch_bounds__(512)
       const bool active = rloc < (int)item.count;
       const int row = (int)item.first + rloc;
       S* tile = (S*)smem_raw + (size_t)rloc * Shifted<Q>::count() * L.nx;
-      if (L.c == CM)
-        fluid_rows_p1<Q, S, SHIFT, CM>(pop, L.nx, L.ny, L.nz, L.pix, row, active, t, tile, p);
-      else if (CM == 4 && L.c == 2)
-        fluid_rows_p1<Q, S, SHIFT, CM == 4 ? 2 : 1>(pop, L.nx, L.ny, L.nz, L.pix, row, active, t,
-                                                    tile, p);
-      else
-        fluid_rows_p1<Q, S, SHIFT, 1>(pop, L.nx, L.ny, L.nz, L.pix, row, active, t, tile, p);
+      fluid_rows_p1<Q, S, SHIFT, LC>(pop, L.nx, L.ny, L.nz, L.pix, row, active, t, tile, p);
       __syncthreads();  // the next item reuses the LDS tile
     }
   }
 }
 
+// Phase 0 over every item, or phase 1 over the items of lane width lc.
 template <int Q, typename S, bool SHIFT>
-void launch_batch(const void* base, const BatchItem* items, int nitems, int phase, int grid,
-                  int threads, hipStream_t stream) {
+void launch_batch(const void* base, const BatchItem* items, int nitems, int phase, int lc,
+                  int grid, int threads, hipStream_t stream) {
+  constexpr int CM = Pack8<S>::C;
   if (phase == 0) {
-    hipLaunchKernelGGL((batch_step_kernel<Q, S, SHIFT, 0>), dim3(grid), dim3(threads), 0, stream,
-                       (S*)base, items, nitems);
-  } else {
-    const size_t lds = (size_t)threads * Pack8<S>::C * Shifted<Q>::count() * sizeof(S);
-    hipLaunchKernelGGL((batch_step_kernel<Q, S, SHIFT, 1>), dim3(grid), dim3(threads), lds,
+    hipLaunchKernelGGL((batch_step_kernel<Q, S, SHIFT, 0, CM>), dim3(grid), dim3(threads), 0,
                        stream, (S*)base, items, nitems);
+    return;
   }
+  const size_t lds = (size_t)threads * CM * Shifted<Q>::count() * sizeof(S);
+  if (lc == CM)
+    hipLaunchKernelGGL((batch_step_kernel<Q, S, SHIFT, 1, CM>), dim3(grid), dim3(threads), lds,
+                       stream, (S*)base, items, nitems);
+  else if (CM == 4 && lc == 2)
+    hipLaunchKernelGGL((batch_step_kernel<Q, S, SHIFT, 1, (CM == 4 ? 2 : 1)>), dim3(grid),
+                       dim3(threads), lds, stream, (S*)base, items, nitems);
+  else
+    hipLaunchKernelGGL((batch_step_kernel<Q, S, SHIFT, 1, 1>), dim3(grid), dim3(threads), lds,
+                       stream, (S*)base, items, nitems);
 }
 
-using LaunchFn = void (*)(const void*, const BatchItem*, int, int, int, int, hipStream_t);
+using LaunchFn = void (*)(const void*, const BatchItem*, int, int, int, int, int, hipStream_t);
 
 template <int Q, bool SHIFT>
 LaunchFn launch_for_storage(int s) {
@@ -207,6 +213,9 @@ struct lbm_batch {
   std::vector<BatchLat> lats;
   long long total_cells = 0;
   int threads = 256, blocks_per_cu = 8, nitems0 = 0, nitems1 = 0;
+  // phase-1 items by lane width: the table holds the items of width lane_c[k]
+  // at lane_first[k] .. lane_first[k] + lane_n[k] - 1 (widest first)
+  int lane_c[3] = {0, 0, 0}, lane_first[3] = {0, 0, 0}, lane_n[3] = {0, 0, 0};
   int max_tpr = 1;  // widest row in lanes: blocks need at least this many threads
   int graph_steps = 0;
   hipGraphExec_t graph = nullptr;
@@ -262,6 +271,20 @@ lbm_status build_items(lbm_batch* b, int threads) {
       i1.push_back(it);
     }
   }
+  // group the phase-1 items by lane width (one launch per width)
+  std::stable_sort(i1.begin(), i1.end(),
+                   [](const BatchItem& a, const BatchItem& c) { return a.c > c.c; });
+  int nk = 0;
+  for (size_t k = 0; k < i1.size(); ++k) {
+    if (k == 0 || i1[k].c != i1[k - 1].c) {
+      b->lane_c[nk] = i1[k].c;
+      b->lane_first[nk] = (int)k;
+      b->lane_n[nk] = 0;
+      ++nk;
+    }
+    ++b->lane_n[nk - 1];
+  }
+  for (int k = nk; k < 3; ++k) b->lane_c[k] = b->lane_first[k] = b->lane_n[k] = 0;
   if (i0.size() > b->lay.max_items0 || i1.size() > b->lay.max_items1)
     return bfail(b, LBM_ERR_ARG, "item table overflow");
   BHIP_TRY(b, hipMemcpyAsync(b->aux + b->lay.items0_off, i0.data(), sizeof(BatchItem) * i0.size(),
@@ -278,11 +301,20 @@ lbm_status build_items(lbm_batch* b, int threads) {
 
 void launch_one(lbm_batch* b, int phase) {
   const LaunchFn fn = launcher(b->q, b->storage, b->shifted);
-  const int n = phase == 0 ? b->nitems0 : b->nitems1;
-  const size_t off = phase == 0 ? b->lay.items0_off : b->lay.items1_off;
-  const int grid = b->blocks_per_cu == 0 ? std::max(1, n)
-                                         : std::max(1, std::min(n, b->blocks_per_cu * b->num_cu));
-  fn(b->pop, (const BatchItem*)(b->aux + off), n, phase, grid, b->threads, b->stream);
+  auto grid_for = [&](int n) {
+    return b->blocks_per_cu == 0 ? std::max(1, n)
+                                 : std::max(1, std::min(n, b->blocks_per_cu * b->num_cu));
+  };
+  if (phase == 0) {
+    fn(b->pop, (const BatchItem*)(b->aux + b->lay.items0_off), b->nitems0, 0, 0,
+       grid_for(b->nitems0), b->threads, b->stream);
+    return;
+  }
+  const BatchItem* items1 = (const BatchItem*)(b->aux + b->lay.items1_off);
+  for (int k = 0; k < 3; ++k)
+    if (b->lane_n[k] > 0)
+      fn(b->pop, items1 + b->lane_first[k], b->lane_n[k], 1, b->lane_c[k], grid_for(b->lane_n[k]),
+         b->threads, b->stream);
 }
 
 lbm_status benter(lbm_batch* b) {
