@@ -204,11 +204,14 @@ lbm_status lbm_lattice_destroy(lbm_lattice* h);
  * Batched ensembles.  `count` fully fluid lattices, periodic on every axis,
  * of uneven shapes dims[3*l .. 3*l+2] = (nx, ny, nz) and relaxation times
  * tau[l], share one population buffer and one aux buffer (both caller-owned,
- * sized by lbm_batch_required_bytes) and advance together: each time step is
- * ONE persistent launch that walks a work list of (lattice, cell range)
- * items, and runs of steps replay as a captured HIP graph.  The update of
- * every cell is the single-lattice collide-and-stream (same kernels' cell
- * arithmetic, same in-place AA layout).  No body force, no walls.
+ * sized by lbm_batch_required_bytes) and advance together: each time step
+ * walks a work list of (lattice, cell range) items in one launch (one per
+ * row width class in the second propagation phase), and runs of steps replay
+ * as a captured HIP graph.  The update of every cell is the single-lattice
+ * collide-and-stream (same cell arithmetic, same in-place AA layout).  No
+ * body force, no walls.  With 16-bit storage, a member whose nx is odd keeps
+ * one padding slot after every x-row in the population buffer (rows nx + 1
+ * slots apart); the member calls below read and write cells only.
  *
  * Each member is also an ordinary lattice handle (lbm_batch_lattice): use
  * lbm_init_equilibrium / lbm_set_populations / lbm_get_populations /

@@ -29,7 +29,8 @@ namespace {
 struct BatchLat {
   uint64_t pop_off;  // element offset of the lattice's populations in the batch buffer
   int nx, ny, nz;
-  uint32_t N;  // cells
+  int px;      // cells from one stored x-row to the next (member_pitch)
+  uint32_t N;  // stored cells, px ny nz (phase 0 also runs over the padding slots)
   PopIndex pix;  // placement of the lattice's populations
   double omega;
   int c;    // phase-1 cells per lane (row_lane_cells); phase 0 always moves 8 bytes a lane
@@ -41,7 +42,7 @@ struct BatchLat {
 struct BatchItem {
   uint64_t pop_off;
   double omega;
-  uint32_t N;
+  int px;
   PopIndex pix;
   int nx, ny, nz;
   int c, tpr;
@@ -80,8 +81,10 @@ __global__ void __launch_bounds__(512)
       const int t = (int)threadIdx.x - rloc * L.tpr;
       const bool active = rloc < (int)item.count;
       const int row = (int)item.first + rloc;
-      S* tile = (S*)smem_raw + (size_t)rloc * Shifted<Q>::count() * L.nx;
-      fluid_rows_p1<Q, S, SHIFT, LC>(pop, L.nx, L.ny, L.nz, L.pix, row, active, t, tile, p);
+      S* tile = (S*)smem_raw + (size_t)rloc * Shifted<Q>::count() * L.px;
+      // only 16-bit members have padded rows (member_pitch)
+      fluid_rows_p1<Q, S, SHIFT, LC, sizeof(S) == 2>(pop, L.nx, L.px, L.ny, L.nz, L.pix, row,
+                                                     active, t, tile, p);
       __syncthreads();  // the next item reuses the LDS tile
     }
   }
@@ -126,17 +129,27 @@ LaunchFn launcher(int q, int storage, bool shifted) {
   return shifted ? launch_for_storage<19, true>(storage) : launch_for_storage<19, false>(storage);
 }
 
+constexpr int MIN_THREADS = 128;  // smallest block; sizes the phase-0 item table
+constexpr int MAX_THREADS = 512;
+
+// Stored row pitch of a member with rows of nx cells in s-byte storage: odd
+// rows of 16-bit storage get one padding slot, so that they too move 2 cells
+// (4 bytes) a lane in phase 1 instead of 1 (phase 1 FP16 on the ensemble,
+// 1-cell rows 4.4 TB/s against 5.9 for 2-cell rows).
+int member_pitch(int nx, size_t s) { return (s == 2 && nx % 2 == 1) ? nx + 1 : nx; }
+
 // Phase-1 cells per lane for rows of nx cells in s-byte storage: the widest
-// aligned lane (8, then 4 bytes) whose cell count divides nx, else 1.
+// aligned lane (8, then 4 bytes) whose cell count divides nx, else 1; except
+// that 16-bit rows take 2 cells (4 bytes) a lane wherever a row fits the
+// block, measured faster than 4 on the ensemble (phase 1 FP16 432 -> 408-415
+// us), whose row body needs 162 VGPRs against 93.
 int row_lane_cells(int nx, size_t s) {
   const int cmax = 8 / (int)s;
+  if (cmax == 4 && nx % 2 == 0 && nx / 2 <= MAX_THREADS) return 2;
   if (nx % cmax == 0) return cmax;
   if (cmax == 4 && nx % 2 == 0) return 2;
   return 1;
 }
-
-constexpr int MIN_THREADS = 128;  // smallest block; sizes the phase-0 item table
-constexpr int MAX_THREADS = 512;
 const int THREAD_CHOICES[] = {128, 256, 512};
 // 0 = one block per item (the grid covers the whole work list); otherwise
 // that many resident blocks per compute unit loop over the items
@@ -161,7 +174,8 @@ lbm_status batch_layout(lbm_descriptor d, int count, const int* dims, lbm_storag
   size_t pop = 0, aux = 0, items0 = 0, items1 = 0, max_cells = 0;
   for (int b = 0; b < count; ++b) {
     size_t pb = 0;
-    lbm_status st = lbm_required_bytes(d, dims[3 * b], dims[3 * b + 1], dims[3 * b + 2], s, &pb, nullptr);
+    const int px = dims[3 * b] > 0 ? member_pitch(dims[3 * b], storage_bytes(s)) : dims[3 * b];
+    lbm_status st = lbm_required_bytes(d, px, dims[3 * b + 1], dims[3 * b + 2], s, &pb, nullptr);
     if (st) {
       *why = "lattice " + std::to_string(b) + ": " + lbm_last_error(nullptr);
       return st;
@@ -175,13 +189,14 @@ lbm_status batch_layout(lbm_descriptor d, int count, const int* dims, lbm_storag
     pop += pb;  // each part is a multiple of 256 bytes
     aux += ab;
     max_cells = std::max(max_cells, N);
-    const int lanes = dims[3 * b] / row_lane_cells(dims[3 * b], storage_bytes(s));
+    const int lanes = px / row_lane_cells(px, storage_bytes(s));
     if (lanes > MAX_THREADS) {
       *why = "lattice " + std::to_string(b) + ": an x-row needs " + std::to_string(lanes) +
              " lanes, more than " + std::to_string(MAX_THREADS);
       return LBM_ERR_UNSUPPORTED;
     }
-    items0 += (N + MIN_THREADS - 1) / MIN_THREADS;  // at least one lane-cell per thread
+    // at least one lane-cell per thread, over the stored cells
+    items0 += ((size_t)px * dims[3 * b + 1] * dims[3 * b + 2] + MIN_THREADS - 1) / MIN_THREADS;
     items1 += (size_t)dims[3 * b + 1] * dims[3 * b + 2];  // at most one row per item
   }
   if (pop / storage_bytes(s) >= 4294967296.0) {
@@ -256,7 +271,7 @@ lbm_status build_items(lbm_batch* b, int threads) {
   i1.reserve(b->lay.max_items1);
   for (int l = 0; l < b->count; ++l) {
     const BatchLat& L = b->lats[l];
-    BatchItem it{L.pop_off, L.omega, L.N, L.pix, L.nx, L.ny, L.nz, L.c, L.tpr, 0, 0};
+    BatchItem it{L.pop_off, L.omega, L.px, L.pix, L.nx, L.ny, L.nz, L.c, L.tpr, 0, 0};
     const uint32_t chunk = (uint32_t)threads * (uint32_t)(8 / storage_bytes(b->storage));
     for (uint32_t c = 0; c < L.N; c += chunk) {
       it.first = c;
@@ -443,11 +458,12 @@ lbm_status lbm_batch_create(lbm_batch** out, lbm_descriptor d, int count, const 
   for (int l = 0; l < count; ++l) {
     const int nx = dims[3 * l], ny = dims[3 * l + 1], nz = dims[3 * l + 2];
     lbm_lattice* v = nullptr;
+    const int px = member_pitch(nx, storage_bytes(s));
     size_t pb = 0;
-    lbm_required_bytes(d, nx, ny, nz, s, &pb, nullptr);
+    lbm_required_bytes(d, px, ny, nz, s, &pb, nullptr);
     st = lbm_detail::create_lattice(&v, d, nx, ny, nz, tau[l], s, flags, b->pop + L.pop_off[l], pb,
                                     b->aux + L.aux_off[l], L.aux_size[l], hip_stream, 0,
-                                    b->aux + L.scratch_off, L.scratch_bytes);
+                                    b->aux + L.scratch_off, L.scratch_bytes, px);
     if (st) return undo(st, "lattice " + std::to_string(l) + ": " + lbm_last_error(nullptr));
     b->views.push_back(v);
     mat.assign((size_t)nx * ny * nz, 1);  // fully fluid, periodic on every axis
@@ -459,11 +475,12 @@ lbm_status lbm_batch_create(lbm_batch** out, lbm_descriptor d, int count, const 
     bl.nx = nx;
     bl.ny = ny;
     bl.nz = nz;
-    bl.N = (uint32_t)v->N;
+    bl.px = px;
+    bl.N = (uint32_t)((size_t)px * ny * nz);
     bl.pix = v->pix;
     bl.omega = v->omega;
-    bl.c = row_lane_cells(nx, storage_bytes(s));
-    bl.tpr = nx / bl.c;
+    bl.c = row_lane_cells(px, storage_bytes(s));
+    bl.tpr = px / bl.c;
     b->max_tpr = std::max(b->max_tpr, bl.tpr);
     b->lats.push_back(bl);
     b->total_cells += (long long)v->N;

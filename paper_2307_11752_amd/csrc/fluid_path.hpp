@@ -115,11 +115,14 @@ __device__ __forceinline__ void fluid_cells_p0(S* __restrict__ pop, const PopInd
 }
 
 // Phase 1 of x-row `row` (= y + ny z) of a fully fluid periodic lattice, lane
-// t covering cells x = C t .. C t + C - 1.  L places the populations; tile:
-// NS * nx values of LDS for this row.  Contains block barriers: every thread
-// of the block must call it (inactive lanes with active = false).  nx % C == 0.
-template <int Q, typename S, bool SHIFT, int C>
-__device__ __forceinline__ void fluid_rows_p1(S* __restrict__ pop, int nx, int ny, int nz,
+// t covering cells x = C t .. C t + C - 1.  Stored rows are px >= nx cells
+// apart (px % C == 0); with PADDED, the slots x = nx .. px - 1 of each row hold
+// no cell: lanes there compute values nobody reads and send nothing along the
+// row.  L places the populations; tile: NS * px values of LDS for this row.
+// Contains block barriers: every thread of the block must call it (inactive
+// lanes with active = false).
+template <int Q, typename S, bool SHIFT, int C, bool PADDED = false>
+__device__ __forceinline__ void fluid_rows_p1(S* __restrict__ pop, int nx, int px, int ny, int nz,
                                               const PopIndex& L, int row, bool active, int t, S* tile,
                                               const StepParams<typename Store<S>::T>& p) {
   using T = typename Store<S>::T;
@@ -136,12 +139,12 @@ __device__ __forceinline__ void fluid_rows_p1(S* __restrict__ pop, int nx, int n
   if (active) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const uint32_t off = L.cell((uint32_t)nx * (uint32_t)(Y[1 - V::cy[i]] + ny * Z[1 - V::cz[i]]) + x0);
+      const uint32_t off = L.cell((uint32_t)px * (uint32_t)(Y[1 - V::cy[i]] + ny * Z[1 - V::cz[i]]) + x0);
       const R r = __builtin_nontemporal_load(at_byte<R>(pop + (size_t)V::opp[i] * L.pstride, off * (uint32_t)sizeof(S)));
       if (V::cx[i] == 0)
         W::unpack(r, sv[i]);
       else
-        *(typename W::raw*)(tile + Shifted<Q>::rank(i) * nx + x0) = r;
+        *(typename W::raw*)(tile + Shifted<Q>::rank(i) * px + x0) = r;
     }
   }
   __syncthreads();
@@ -153,7 +156,7 @@ __device__ __forceinline__ void fluid_rows_p1(S* __restrict__ pop, int nx, int n
       for (int k = 0; k < C; ++k) {
         int xs = x0 + k - V::cx[i];
         xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-        sv[i][k] = tile[Shifted<Q>::rank(i) * nx + xs];
+        sv[i][k] = tile[Shifted<Q>::rank(i) * px + xs];
       }
     }
 #pragma unroll
@@ -171,14 +174,15 @@ __device__ __forceinline__ void fluid_rows_p1(S* __restrict__ pop, int nx, int n
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       if (V::cx[i] == 0) {
-        const uint32_t off = L.cell((uint32_t)nx * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]) + x0);
+        const uint32_t off = L.cell((uint32_t)px * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]) + x0);
         __builtin_nontemporal_store(W::pack(sv[i]), at_byte<R>(pop + (size_t)i * L.pstride, off * (uint32_t)sizeof(S)));
       } else {
 #pragma unroll
         for (int k = 0; k < C; ++k) {
+          if (PADDED && x0 + k >= nx) continue;  // a padding slot sends nothing
           int xd = x0 + k + V::cx[i];
           xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
-          tile[Shifted<Q>::rank(i) * nx + xd] = sv[i][k];
+          tile[Shifted<Q>::rank(i) * px + xd] = sv[i][k];
         }
       }
     }
@@ -188,8 +192,8 @@ __device__ __forceinline__ void fluid_rows_p1(S* __restrict__ pop, int nx, int n
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       if (V::cx[i] == 0) continue;
-      const uint32_t off = L.cell((uint32_t)nx * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]) + x0);
-      __builtin_nontemporal_store(*(const R*)(tile + Shifted<Q>::rank(i) * nx + x0),
+      const uint32_t off = L.cell((uint32_t)px * (uint32_t)(Y[1 + V::cy[i]] + ny * Z[1 + V::cz[i]]) + x0);
+      __builtin_nontemporal_store(*(const R*)(tile + Shifted<Q>::rank(i) * px + x0),
                                   at_byte<R>(pop + (size_t)i * L.pstride, off * (uint32_t)sizeof(S)));
     }
   }

@@ -94,6 +94,9 @@ inline size_t storage_bytes(int s) {
 struct lbm_lattice {
   int desc = 0, q = 0, nx = 0, ny = 0, nz = 0;
   size_t N = 0;
+  // Cells from one stored x-row to the next: nx, or nx + 1 for a batch member
+  // whose odd rows are padded (the padding slots hold no cell).
+  int px = 0;
   lbm::PopIndex pix{};  // placement of the populations (pop_index)
   int storage = 0;
   bool shifted = false;
@@ -136,11 +139,13 @@ lbm_status fail(lbm_lattice* h, lbm_status st, const std::string& msg);
 void drop_graph(lbm_lattice* h);
 // lbm_lattice_create with an explicit scratch area: own_scratch bytes of the
 // aux buffer (lbm_lattice_create uses scratch_size(N)), or, with
-// own_scratch == 0, the caller's shared scratch of shared_bytes.
+// own_scratch == 0, the caller's shared scratch of shared_bytes; px > nx
+// stores the populations with that row pitch (0 = nx).
 lbm_status create_lattice(lbm_lattice** out, lbm_descriptor d, int nx, int ny, int nz,
                           double tau, lbm_storage s, unsigned flags, void* dev_pop,
                           size_t pop_bytes, void* dev_aux, size_t aux_bytes, void* hip_stream,
-                          size_t own_scratch, unsigned char* shared, size_t shared_bytes);
+                          size_t own_scratch, unsigned char* shared, size_t shared_bytes,
+                          int px = 0);
 }  // namespace lbm_detail
 
 #define HIP_TRY(h, call)                                                                  \

@@ -369,7 +369,8 @@ struct Nbr {
   }
 };
 
-__device__ __forceinline__ Nbr make_nbr(int x, int y, int z, int nx, int ny, int nz) {
+// px: cells from one stored x-row to the next (nx, or more for padded rows).
+__device__ __forceinline__ Nbr make_nbr(int x, int y, int z, int nx, int ny, int nz, int px) {
   Nbr n;
   n.X[0] = x == 0 ? nx - 1 : x - 1;
   n.X[1] = x;
@@ -379,8 +380,11 @@ __device__ __forceinline__ Nbr make_nbr(int x, int y, int z, int nx, int ny, int
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) n.R[a][b] = (uint32_t)nx * (uint32_t)(Y[a] + ny * Z[b]);
+    for (int b = 0; b < 3; ++b) n.R[a][b] = (uint32_t)px * (uint32_t)(Y[a] + ny * Z[b]);
   return n;
+}
+__device__ __forceinline__ Nbr make_nbr(int x, int y, int z, int nx, int ny, int nz) {
+  return make_nbr(x, y, z, nx, ny, nz, nx);
 }
 
 }  // namespace lbm

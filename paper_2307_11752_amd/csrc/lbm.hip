@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(256)
   const int t = (int)threadIdx.x - rloc * tpr;
   const int row = (int)blockIdx.x * rows_per_block + rloc;
   S* tile = (S*)smem_raw + (size_t)rloc * Shifted<Q>::count() * nx;
-  fluid_rows_p1<Q, S, SHIFT, C>(pop, nx, ny, nz, L, row, row < ny * nz, t, tile, p);
+  fluid_rows_p1<Q, S, SHIFT, C>(pop, nx, nx, ny, nz, L, row, row < ny * nz, t, tile, p);
 }
 
 // Phase 1 with each x-row held by 2^lr_log2 = nx / C lanes of one wave (a
@@ -295,13 +295,14 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 // Decoding of the stored state (used off the per-step path).
 // ---------------------------------------------------------------------------
+// sidx: the cell's stored position (x + px (y + ny z)); nb: its neighbours' stored positions.
 template <int Q, typename S>
-__device__ __forceinline__ S load_phase(const S* pop, uint32_t lw, int i, uint32_t idx,
+__device__ __forceinline__ S load_phase(const S* pop, uint32_t lw, int i, uint32_t sidx,
                                         const Nbr& nb, int phase, const PopIndex& L) {
   using V = Vel<Q>;
-  if (phase == 0 || i == 0) return pop[L.at(i, idx)];
+  if (phase == 0 || i == 0) return pop[L.at(i, sidx)];
   const int o = V::opp[i];
-  if ((lw >> (o - 1)) & 1u) return pop[L.at(i, idx)];
+  if ((lw >> (o - 1)) & 1u) return pop[L.at(i, sidx)];
   return pop[L.at(o, nb.at(-V::cx[i], -V::cy[i], -V::cz[i]))];
 }
 
@@ -312,22 +313,30 @@ __device__ __forceinline__ void cell_coords(uint32_t idx, int nx, int ny, int& x
   z = (int)(r / (uint32_t)ny);
 }
 
+// Stored position of cell idx = x + nx (y + ny z) when x-rows are px cells apart.
+__device__ __forceinline__ uint32_t stored_cell(uint32_t idx, int nx, int px) {
+  if (px == nx) return idx;
+  const uint32_t r = idx / (uint32_t)nx;
+  return idx + r * (uint32_t)(px - nx);
+}
+
 // f (double, natural layout, unshifted) of every cell; zeros for non-fluid cells.
 template <int Q, typename S, bool SHIFT>
 __global__ void get_pop_kernel(const S* __restrict__ pop, const uint32_t* __restrict__ link,
-                               double* __restrict__ out, int nx, int ny, int nz, uint32_t N,
-                               PopIndex L, int phase) {
+                               double* __restrict__ out, int nx, int ny, int nz, int px,
+                               uint32_t N, PopIndex L, int phase) {
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
        idx += gridDim.x * blockDim.x) {
     const uint32_t lw = link[idx];
     int x, y, z;
     cell_coords(idx, nx, ny, x, y, z);
-    const Nbr nb = make_nbr(x, y, z, nx, ny, nz);
+    const Nbr nb = make_nbr(x, y, z, nx, ny, nz, px);
+    const uint32_t sidx = stored_cell(idx, nx, px);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       double v = 0.0;
       if (lw & LINK_FLUID) {
-        v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, L));
+        v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, sidx, nb, phase, L));
         if (SHIFT) v += weight<Q, double>(i);
       }
       out[(size_t)i * N + idx] = v;
@@ -337,15 +346,16 @@ __global__ void get_pop_kernel(const S* __restrict__ pop, const uint32_t* __rest
 
 // Populations from double natural layout; phase becomes 0.
 template <int Q, typename S, bool SHIFT>
-__global__ void set_pop_kernel(S* __restrict__ pop, const double* __restrict__ in, uint32_t N,
-                               PopIndex L) {
+__global__ void set_pop_kernel(S* __restrict__ pop, const double* __restrict__ in, int nx, int px,
+                               uint32_t N, PopIndex L) {
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
        idx += gridDim.x * blockDim.x) {
+    const uint32_t sidx = stored_cell(idx, nx, px);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       double v = in[(size_t)i * N + idx];
       if (SHIFT) v -= weight<Q, double>(i);
-      pop[L.at(i, idx)] = Store<S>::from_f64(v);
+      pop[L.at(i, sidx)] = Store<S>::from_f64(v);
     }
   }
 }
@@ -354,11 +364,12 @@ __global__ void set_pop_kernel(S* __restrict__ pop, const double* __restrict__ i
 template <int Q, typename S, bool SHIFT>
 __global__ void init_eq_kernel(S* __restrict__ pop, const uint32_t* __restrict__ link,
                                const double* __restrict__ rho_in, const double* __restrict__ u_in,
-                               uint32_t N, PopIndex L) {
+                               int nx, int px, uint32_t N, PopIndex L) {
   using V = Vel<Q>;
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
        idx += gridDim.x * blockDim.x) {
     const bool fluid = (link[idx] & LINK_FLUID) != 0;
+    const uint32_t sidx = stored_cell(idx, nx, px);
     const double rho = rho_in ? rho_in[idx] : 1.0;
     double u[3] = {0.0, 0.0, 0.0};
     if (u_in)
@@ -370,7 +381,7 @@ __global__ void init_eq_kernel(S* __restrict__ pop, const uint32_t* __restrict__
       const double cu = V::cx[i] * u[0] + V::cy[i] * u[1] + V::cz[i] * u[2];
       double feq = w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
       if (SHIFT) feq -= w;
-      pop[L.at(i, idx)] = Store<S>::from_f64(fluid ? feq : 0.0);
+      pop[L.at(i, sidx)] = Store<S>::from_f64(fluid ? feq : 0.0);
     }
   }
 }
@@ -381,8 +392,9 @@ __global__ void init_eq_kernel(S* __restrict__ pop, const uint32_t* __restrict__
 template <int Q, typename S, bool SHIFT, typename OutT>
 __global__ void moments_kernel(const S* __restrict__ pop, const uint32_t* __restrict__ link,
                                OutT* __restrict__ rho_out, OutT* __restrict__ u_out, int nx,
-                               int ny, int nz, PopIndex L, int phase, double gx, double gy,
-                               double gz, uint32_t begin, uint32_t count, uint32_t ustride) {
+                               int ny, int nz, int px, PopIndex L, int phase, double gx,
+                               double gy, double gz, uint32_t begin, uint32_t count,
+                               uint32_t ustride) {
   using V = Vel<Q>;
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < count;
        k += gridDim.x * blockDim.x) {
@@ -392,11 +404,12 @@ __global__ void moments_kernel(const S* __restrict__ pop, const uint32_t* __rest
     if (lw & LINK_FLUID) {
       int x, y, z;
       cell_coords(idx, nx, ny, x, y, z);
-      const Nbr nb = make_nbr(x, y, z, nx, ny, nz);
+      const Nbr nb = make_nbr(x, y, z, nx, ny, nz, px);
+      const uint32_t sidx = stored_cell(idx, nx, px);
       double sf = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const double v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, L));
+        const double v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, sidx, nb, phase, L));
         sf += v;
         j[0] += V::cx[i] * v;
         j[1] += V::cy[i] * v;
@@ -421,8 +434,8 @@ __global__ void moments_kernel(const S* __restrict__ pop, const uint32_t* __rest
 template <int Q, typename S, bool SHIFT>
 __global__ void __launch_bounds__(RED_THREADS)
     totals_partial_kernel(const S* __restrict__ pop, const uint32_t* __restrict__ link,
-                          double* __restrict__ partials, int nx, int ny, int nz, uint32_t N,
-                          PopIndex L, int phase, double gx, double gy, double gz) {
+                          double* __restrict__ partials, int nx, int ny, int nz, int px,
+                          uint32_t N, PopIndex L, int phase, double gx, double gy, double gz) {
   using V = Vel<Q>;
   double acc[RED_FIELDS] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N;
@@ -431,11 +444,12 @@ __global__ void __launch_bounds__(RED_THREADS)
     if (!(lw & LINK_FLUID)) continue;
     int x, y, z;
     cell_coords(idx, nx, ny, x, y, z);
-    const Nbr nb = make_nbr(x, y, z, nx, ny, nz);
+    const Nbr nb = make_nbr(x, y, z, nx, ny, nz, px);
+    const uint32_t sidx = stored_cell(idx, nx, px);
     double sf = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const double v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, idx, nb, phase, L));
+      const double v = Store<S>::to_f64(load_phase<Q, S>(pop, lw, i, sidx, nb, phase, L));
       sf += v;
       j[0] += V::cx[i] * v;
       j[1] += V::cy[i] * v;
@@ -760,24 +774,24 @@ struct Ops {
   static void get_pop(lbm_lattice* h, double* out) {
     hipLaunchKernelGGL((get_pop_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
                        (const S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), out, h->nx,
-                       h->ny, h->nz, (uint32_t)h->N, h->pix, h->phase);
+                       h->ny, h->nz, h->px, (uint32_t)h->N, h->pix, h->phase);
   }
   static void set_pop(lbm_lattice* h, const double* in) {
     hipLaunchKernelGGL((set_pop_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
-                       (S*)h->pop, in, (uint32_t)h->N, h->pix);
+                       (S*)h->pop, in, h->nx, h->px, (uint32_t)h->N, h->pix);
   }
   static void init_eq(lbm_lattice* h, const double* rho, const double* u) {
     hipLaunchKernelGGL((init_eq_kernel<Q, S, SHIFT>), dim3(blocks(h->N)), dim3(256), 0, h->stream,
-                       (S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), rho, u,
-                       (uint32_t)h->N, h->pix);
+                       (S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), rho, u, h->nx,
+                       h->px, (uint32_t)h->N, h->pix);
   }
   template <typename OutT>
   static void moments(lbm_lattice* h, OutT* rho, OutT* u, uint32_t begin, uint32_t count,
                       uint32_t ustride) {
     hipLaunchKernelGGL((moments_kernel<Q, S, SHIFT, OutT>), dim3(blocks(count)), dim3(256), 0,
                        h->stream, (const S*)h->pop, (const uint32_t*)(h->aux + h->lay.link), rho,
-                       u, h->nx, h->ny, h->nz, h->pix, h->phase, h->g[0], h->g[1], h->g[2],
-                       begin, count, ustride);
+                       u, h->nx, h->ny, h->nz, h->px, h->pix, h->phase, h->g[0], h->g[1],
+                       h->g[2], begin, count, ustride);
   }
   static void moments_f64(lbm_lattice* h, double* rho, double* u, uint32_t begin, uint32_t count,
                           uint32_t ustride) {
@@ -790,7 +804,7 @@ struct Ops {
   static void totals(lbm_lattice* h, double* partials, double* result) {
     hipLaunchKernelGGL((totals_partial_kernel<Q, S, SHIFT>), dim3(RED_BLOCKS), dim3(RED_THREADS),
                        0, h->stream, (const S*)h->pop, (const uint32_t*)(h->aux + h->lay.link),
-                       partials, h->nx, h->ny, h->nz, (uint32_t)h->N, h->pix, h->phase,
+                       partials, h->nx, h->ny, h->nz, h->px, (uint32_t)h->N, h->pix, h->phase,
                        h->g[0], h->g[1], h->g[2]);
     hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(RED_THREADS), 0, h->stream, partials,
                        result, RED_BLOCKS);
@@ -1009,11 +1023,14 @@ lbm_status lbm_detail::create_lattice(lbm_lattice** out, lbm_descriptor d, int n
                                       double tau, lbm_storage s, unsigned flags, void* dev_pop,
                                       size_t pop_bytes, void* dev_aux, size_t aux_bytes,
                                       void* hip_stream, size_t own_scratch, unsigned char* shared,
-                                      size_t shared_bytes) {
+                                      size_t shared_bytes, int px) {
   if (!out) return fail(nullptr, LBM_ERR_ARG, "out is NULL");
   *out = nullptr;
+  const int pitch = px > 0 ? px : nx;
+  if (pitch < nx) return fail(nullptr, LBM_ERR_ARG, "row pitch below nx");
   size_t need_pop = 0;
-  lbm_status st = lbm_required_bytes(d, nx, ny, nz, s, &need_pop, nullptr);
+  // the populations are stored as a lattice of pitch x ny x nz cells
+  lbm_status st = lbm_required_bytes(d, pitch, ny, nz, s, &need_pop, nullptr);
   if (st) return st;
   const size_t need_aux = aux_layout((size_t)nx * ny * nz, own_scratch).total;
   if (own_scratch == 0 && (!shared || shared_bytes < SCRATCH_MIN))
@@ -1035,7 +1052,8 @@ lbm_status lbm_detail::create_lattice(lbm_lattice** out, lbm_descriptor d, int n
   h->ny = ny;
   h->nz = nz;
   h->N = (size_t)nx * ny * nz;
-  h->pix = pop_index(h->q, h->N, storage_bytes(s));
+  h->px = pitch;
+  h->pix = pop_index(h->q, (size_t)pitch * ny * nz, storage_bytes(s));
   h->storage = s;
   h->shifted = (flags & LBM_FLAG_SHIFTED) != 0;
   h->tau = tau;
