@@ -260,8 +260,9 @@ def oracle_field_errors(args, wl, make_lattice, storage, shifted):
 
 def bench_ensemble(args):
     """Batched ensemble: 256 periodic D3Q19 Taylor-Green lattices, edges
-    log-uniform 16-96 (seeded), u0 in [0.01, 0.08], tau in [0.55, 1.0]; one
-    persistent launch per step, 100-step graph replay, autotuned launch shape."""
+    log-uniform 16-96 (seeded), u0 in [0.01, 0.08], tau in [0.55, 1.0]; every
+    member advanced by the batch's launches (one per phase and lane width),
+    100-step graph replay, autotuned launch shape."""
     import numpy as np
     import torch
 

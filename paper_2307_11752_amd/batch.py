@@ -1,7 +1,8 @@
 """Batched ensembles of periodic lattices (C ABI ``lbm_batch_*``).
 
-One persistent launch per time step advances every member; runs of steps are
-replayed from a captured HIP graph; ``autotune()`` picks the launch shape by
+Each time step advances every member through the batch's own launches (one
+per propagation phase, and per row width class in the second); runs of steps
+are replayed from a captured HIP graph; ``autotune()`` picks the launch shape by
 measurement.  Members are lattice handles: read them with the ``Lattice``
 calls (``init_equilibrium``, ``moments``, ``totals``, ``get_populations``).
 """

@@ -292,6 +292,7 @@ lbm_status build_items(lbm_batch* b, int threads) {
   int nk = 0;
   for (size_t k = 0; k < i1.size(); ++k) {
     if (k == 0 || i1[k].c != i1[k - 1].c) {
+      if (nk == 3) return bfail(b, LBM_ERR_ARG, "more than three lane widths");  // 1, 2 and 4 only
       b->lane_c[nk] = i1[k].c;
       b->lane_first[nk] = (int)k;
       b->lane_n[nk] = 0;
