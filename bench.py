@@ -282,7 +282,7 @@ def bench_ensemble(args):
             m.init_equilibrium(None, u)
 
     init()
-    threads, bpc, tuned_ms = batch.autotune(trial_steps=10)
+    tuned_ms = batch.autotune(trial_steps=10)[2]
     init()
     if args.graph_steps:
         batch.set_graph_steps(args.graph_steps)
@@ -336,6 +336,9 @@ def bench_ensemble(args):
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
     mlups = cells * args.steps / wall / 1e6
 
+    shapes_used = {f"phase{ph}": dict(zip(("threads", "blocks_per_cu"), batch.phase_launch(ph)))
+                   for ph in (0, 1)}
+
     # the same lattices stepped one by one (each its own handle, launches and
     # 100-step graph) -- what the batch replaces
     batch.close()
@@ -377,8 +380,7 @@ def bench_ensemble(args):
                                "log-uniform 16-96 (seed 1107), u0 U[0.01,0.08], tau U[0.55,1.0]",
                    "lattices": len(shapes), "cells": cells,
                    "storage": storage + ("-shifted" if shifted else ""),
-                   "launch": {"threads": threads, "blocks_per_cu": bpc,
-                              "autotune_ms_per_step": round(tuned_ms, 5)},
+                   "launch": {**shapes_used, "autotune_ms_per_step": round(tuned_ms, 5)},
                    "graph_steps": args.graph_steps},
         "kernel_ms_per_step": round(kernel_ms, 5),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

@@ -243,21 +243,37 @@ lbm_status lbm_batch_step(lbm_batch* b, int n);
 /* As lbm_set_graph_steps, for the batch launch. */
 lbm_status lbm_batch_set_graph_steps(lbm_batch* b, int steps);
 
-/* Launch shape: threads per block (128, 256 or 512, at least the widest
- * row's lanes; a phase-0 item is a run of that many lanes of cells, a
- * phase-1 item as many whole x-rows as fit) and resident blocks per compute
- * unit of the persistent grid (1..64), or 0 for one block per work item. */
+/* Launch shape of both propagation phases: threads per block (128, 256 or
+ * 512; a phase-0 item is a run of that many lanes of cells, a phase-1 item as
+ * many whole x-rows as fit, so phase 1 needs at least the widest row's lanes)
+ * and resident blocks per compute unit of the persistent grid (1..64), or 0
+ * for one block per work item.  LBM_ERR_ARG for any other value. */
 lbm_status lbm_batch_set_launch(lbm_batch* b, int threads, int blocks_per_cu);
 
+/* The same for one phase (0 or 1) only; the other keeps its shape.  The two
+ * phases are separate launches with different bodies (phase 0 local to each
+ * cell, phase 1 over whole x-rows), and their fastest shapes differ. */
+lbm_status lbm_batch_set_phase_launch(lbm_batch* b, int phase, int threads, int blocks_per_cu);
+
+/* Current shape of one phase (0 or 1).  Host only. */
+lbm_status lbm_batch_get_phase_launch(const lbm_batch* b, int phase, int* threads,
+                                      int* blocks_per_cu);
+
 /* Measure every launch shape in the built-in candidate set (threads 128 /
- * 256 / 512 x blocks per CU 0 / 2 / 4 / 8 / 16) over trial_steps (even) timed
- * steps each, keep the fastest, and report it.  Members must be initialised
- * (any state will do); every candidate advances them by trial_steps + 2
- * steps (the propagation phase is kept), so initialise them again afterwards.
- * sync. */
+ * 256 / 512 x blocks per CU 0 / 2 / 4 / 8 / 16) for both phases over
+ * trial_steps (even) timed steps each, timing the two phases' launches apart;
+ * then time each phase's fastest shape combined, and keep that combination if
+ * it beats the fastest common shape, else the common shape (read the result
+ * with lbm_batch_get_phase_launch).  Reports phase 1's shape in *threads /
+ * *blocks_per_cu and the kept shapes' measured ms per step as
+ * *best_ms_per_step (any output may be NULL).
+ * Members must be initialised (any state will do); every candidate advances
+ * them by trial_steps + 2 steps (the propagation phase is kept), so
+ * initialise them again afterwards.  sync. */
 lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* threads, int* blocks_per_cu,
                               double* best_ms_per_step);
 
+/* Member count, total cells, and phase 1's launch shape. */
 lbm_status lbm_batch_get_info(const lbm_batch* b, int* count, long long* total_cells,
                               int* threads, int* blocks_per_cu);
 

@@ -68,6 +68,8 @@ SIGNATURES = {
     "lbm_batch_step": ([_P, _I], _I),
     "lbm_batch_set_graph_steps": ([_P, _I], _I),
     "lbm_batch_set_launch": ([_P, _I, _I], _I),
+    "lbm_batch_set_phase_launch": ([_P, _I, _I, _I], _I),
+    "lbm_batch_get_phase_launch": ([_P, _I, _PI, _PI], _I),
     "lbm_batch_autotune": ([_P, _I, _PI, _PI, _PD], _I),
     "lbm_batch_get_info": ([_P, _PI, _PLL, _PI, _PI], _I),
     "lbm_batch_destroy": ([_P], _I),

@@ -95,11 +95,26 @@ class Batch:
         self._chk(self.lib.lbm_batch_set_graph_steps(self.h, int(steps)))
 
     def set_launch(self, threads, blocks_per_cu):
+        """Launch shape of both propagation phases (lbm_batch_set_launch)."""
         self._chk(self.lib.lbm_batch_set_launch(self.h, int(threads), int(blocks_per_cu)))
 
+    def set_phase_launch(self, phase, threads, blocks_per_cu):
+        """Launch shape of one phase (0 or 1) only (lbm_batch_set_phase_launch)."""
+        self._chk(self.lib.lbm_batch_set_phase_launch(self.h, int(phase), int(threads),
+                                                      int(blocks_per_cu)))
+
+    def phase_launch(self, phase):
+        """(threads, blocks_per_cu) of one phase (lbm_batch_get_phase_launch)."""
+        t, b = ctypes.c_int(), ctypes.c_int()
+        self._chk(self.lib.lbm_batch_get_phase_launch(self.h, int(phase), ctypes.byref(t),
+                                                      ctypes.byref(b)))
+        return t.value, b.value
+
     def autotune(self, trial_steps=20):
-        """Measure the built-in launch shapes and keep the fastest.  Advances
-        every member (call before initialising the populations)."""
+        """Measure the built-in launch shapes and keep the fastest of each phase
+        (read them with phase_launch).  Returns phase 1's threads and blocks per
+        CU and the tuned ms per step.  Advances every member (initialise the
+        populations again afterwards)."""
         t, b, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         self._chk(self.lib.lbm_batch_autotune(self.h, int(trial_steps), ctypes.byref(t),
                                               ctypes.byref(b), ctypes.byref(ms)))

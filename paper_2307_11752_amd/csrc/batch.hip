@@ -82,9 +82,11 @@ __global__ void __launch_bounds__(512)
       const bool active = rloc < (int)item.count;
       const int row = (int)item.first + rloc;
       S* tile = (S*)smem_raw + (size_t)rloc * Shifted<Q>::count() * L.px;
-      // only 16-bit members have padded rows (member_pitch)
-      fluid_rows_p1<Q, S, SHIFT, LC, sizeof(S) == 2>(pop, L.nx, L.px, L.ny, L.nz, L.pix, row,
-                                                     active, t, tile, p);
+      // only 16-bit members have padded rows (member_pitch).  FP32 rows load
+      // through the caches (measured: ensemble phase 1 755 -> 721 us; 16-bit
+      // storage gains nothing, and the single lattice's 256-cell rows lose)
+      fluid_rows_p1<Q, S, SHIFT, LC, sizeof(S) == 2, sizeof(S) != 4>(
+          pop, L.nx, L.px, L.ny, L.nz, L.pix, row, active, t, tile, p);
       __syncthreads();  // the next item reuses the LDS tile
     }
   }
@@ -227,7 +229,10 @@ struct lbm_batch {
   std::vector<lbm_lattice*> views;
   std::vector<BatchLat> lats;
   long long total_cells = 0;
-  int threads = 256, blocks_per_cu = 8, nitems0 = 0, nitems1 = 0;
+  // launch shape per propagation phase: threads per block and resident
+  // blocks per CU (0 = one block per work item)
+  int threads[2] = {256, 256}, blocks_per_cu[2] = {8, 8};
+  int nitems0 = 0, nitems1 = 0;
   // phase-1 items by lane width: the table holds the items of width lane_c[k]
   // at lane_first[k] .. lane_first[k] + lane_n[k] - 1 (widest first)
   int lane_c[3] = {0, 0, 0}, lane_first[3] = {0, 0, 0}, lane_n[3] = {0, 0, 0};
@@ -260,11 +265,11 @@ void drop_batch_graph(lbm_batch* b) {
   }
 }
 
-// Cut every lattice into phase-0 items (runs of threads lanes of 8 bytes) and
-// phase-1 items (as many whole x-rows as threads lanes hold).
-lbm_status build_items(lbm_batch* b, int threads) {
-  if (threads < b->max_tpr)
-    return bfail(b, LBM_ERR_ARG, "threads per block must cover the widest row (" +
+// Cut every lattice into phase-0 items (runs of t0 lanes of 8 bytes) and
+// phase-1 items (as many whole x-rows as t1 lanes hold).
+lbm_status build_items(lbm_batch* b, int t0, int t1) {
+  if (t1 < b->max_tpr)
+    return bfail(b, LBM_ERR_ARG, "phase-1 threads per block must cover the widest row (" +
                                      std::to_string(b->max_tpr) + " lanes)");
   std::vector<BatchItem> i0, i1;
   i0.reserve(b->lay.max_items0);
@@ -272,14 +277,14 @@ lbm_status build_items(lbm_batch* b, int threads) {
   for (int l = 0; l < b->count; ++l) {
     const BatchLat& L = b->lats[l];
     BatchItem it{L.pop_off, L.omega, L.px, L.pix, L.nx, L.ny, L.nz, L.c, L.tpr, 0, 0};
-    const uint32_t chunk = (uint32_t)threads * (uint32_t)(8 / storage_bytes(b->storage));
+    const uint32_t chunk = (uint32_t)t0 * (uint32_t)(8 / storage_bytes(b->storage));
     for (uint32_t c = 0; c < L.N; c += chunk) {
       it.first = c;
       it.count = std::min<uint32_t>(chunk, L.N - c);
       i0.push_back(it);
     }
     const uint32_t rows = (uint32_t)L.ny * (uint32_t)L.nz;
-    const uint32_t per = (uint32_t)(threads / L.tpr);
+    const uint32_t per = (uint32_t)(t1 / L.tpr);
     for (uint32_t r = 0; r < rows; r += per) {
       it.first = r;
       it.count = std::min<uint32_t>(per, rows - r);
@@ -310,27 +315,28 @@ lbm_status build_items(lbm_batch* b, int threads) {
   BHIP_TRY(b, hipStreamSynchronize(b->stream));
   b->nitems0 = (int)i0.size();
   b->nitems1 = (int)i1.size();
-  b->threads = threads;
+  b->threads[0] = t0;
+  b->threads[1] = t1;
   drop_batch_graph(b);
   return LBM_OK;
 }
 
 void launch_one(lbm_batch* b, int phase) {
   const LaunchFn fn = launcher(b->q, b->storage, b->shifted);
+  const int bpc = b->blocks_per_cu[phase];
   auto grid_for = [&](int n) {
-    return b->blocks_per_cu == 0 ? std::max(1, n)
-                                 : std::max(1, std::min(n, b->blocks_per_cu * b->num_cu));
+    return bpc == 0 ? std::max(1, n) : std::max(1, std::min(n, bpc * b->num_cu));
   };
   if (phase == 0) {
     fn(b->pop, (const BatchItem*)(b->aux + b->lay.items0_off), b->nitems0, 0, 0,
-       grid_for(b->nitems0), b->threads, b->stream);
+       grid_for(b->nitems0), b->threads[0], b->stream);
     return;
   }
   const BatchItem* items1 = (const BatchItem*)(b->aux + b->lay.items1_off);
   for (int k = 0; k < 3; ++k)
     if (b->lane_n[k] > 0)
       fn(b->pop, items1 + b->lane_first[k], b->lane_n[k], 1, b->lane_c[k], grid_for(b->lane_n[k]),
-         b->threads, b->stream);
+         b->threads[1], b->stream);
 }
 
 lbm_status benter(lbm_batch* b) {
@@ -488,7 +494,8 @@ lbm_status lbm_batch_create(lbm_batch** out, lbm_descriptor d, int count, const 
   }
   int t0 = 128;
   while (t0 < b->max_tpr) t0 *= 2;
-  st = build_items(b, std::max(256, t0));
+  t0 = std::max(256, t0);
+  st = build_items(b, t0, t0);
   if (st) return undo(st, b->err);
   *out = b;
   return LBM_OK;
@@ -501,17 +508,53 @@ lbm_status lbm_batch_lattice(lbm_batch* b, int index, lbm_lattice** view) {
   return LBM_OK;
 }
 
-lbm_status lbm_batch_set_launch(lbm_batch* b, int threads, int blocks_per_cu) {
-  lbm_status st = benter(b);
-  if (st) return st;
+namespace {
+
+lbm_status check_shape(lbm_batch* b, int threads, int blocks_per_cu) {
   bool ok = false;
   for (int t : THREAD_CHOICES) ok |= t == threads;
   if (!ok) return bfail(b, LBM_ERR_ARG, "threads must be 128, 256 or 512");
   if (blocks_per_cu < 0 || blocks_per_cu > 64)
     return bfail(b, LBM_ERR_ARG, "blocks_per_cu in 0..64 (0 = one block per work item)");
-  b->blocks_per_cu = blocks_per_cu;
-  if (threads != b->threads) return build_items(b, threads);
+  return LBM_OK;
+}
+
+// Both phases' shapes at once; the item tables are rebuilt when a thread
+// count changes.
+lbm_status apply_shapes(lbm_batch* b, const int (&threads)[2], const int (&bpc)[2]) {
+  b->blocks_per_cu[0] = bpc[0];
+  b->blocks_per_cu[1] = bpc[1];
+  if (threads[0] != b->threads[0] || threads[1] != b->threads[1])
+    return build_items(b, threads[0], threads[1]);
   drop_batch_graph(b);
+  return LBM_OK;
+}
+
+}  // namespace
+
+lbm_status lbm_batch_set_launch(lbm_batch* b, int threads, int blocks_per_cu) {
+  lbm_status st = benter(b);
+  if (st) return st;
+  if ((st = check_shape(b, threads, blocks_per_cu))) return st;
+  return apply_shapes(b, {threads, threads}, {blocks_per_cu, blocks_per_cu});
+}
+
+lbm_status lbm_batch_set_phase_launch(lbm_batch* b, int phase, int threads, int blocks_per_cu) {
+  lbm_status st = benter(b);
+  if (st) return st;
+  if (phase != 0 && phase != 1) return bfail(b, LBM_ERR_ARG, "phase must be 0 or 1");
+  if ((st = check_shape(b, threads, blocks_per_cu))) return st;
+  int t[2] = {b->threads[0], b->threads[1]}, c[2] = {b->blocks_per_cu[0], b->blocks_per_cu[1]};
+  t[phase] = threads;
+  c[phase] = blocks_per_cu;
+  return apply_shapes(b, t, c);
+}
+
+lbm_status lbm_batch_get_phase_launch(const lbm_batch* b, int phase, int* threads,
+                                      int* blocks_per_cu) {
+  if (!b || (phase != 0 && phase != 1)) return LBM_ERR_ARG;
+  if (threads) *threads = b->threads[phase];
+  if (blocks_per_cu) *blocks_per_cu = b->blocks_per_cu[phase];
   return LBM_OK;
 }
 
@@ -550,6 +593,37 @@ lbm_status lbm_batch_set_graph_steps(lbm_batch* b, int steps) {
   return LBM_OK;
 }
 
+namespace {
+
+// Two untimed steps, then trial_steps timed ones (an even count: the
+// propagation phase is unchanged) with an event after every launch; ms[ph]
+// receives the mean time of phase ph's launches and *total the mean step.
+lbm_status time_trial(lbm_batch* b, int phase, int trial_steps, std::vector<hipEvent_t>& ev,
+                      double (&ms)[2], double* total) {
+  launch_one(b, phase);
+  launch_one(b, phase ^ 1);
+  (void)hipEventRecord(ev[0], b->stream);
+  for (int s = 0; s < trial_steps; ++s) {
+    launch_one(b, phase ^ (s & 1));
+    (void)hipEventRecord(ev[s + 1], b->stream);
+  }
+  if (hipEventSynchronize(ev[trial_steps]) != hipSuccess)
+    return bfail(b, LBM_ERR_HIP, "autotune trial failed");
+  ms[0] = ms[1] = 0.0;
+  for (int s = 0; s < trial_steps; ++s) {
+    float m = 0.f;
+    (void)hipEventElapsedTime(&m, ev[s], ev[s + 1]);
+    ms[phase ^ (s & 1)] += m;
+  }
+  ms[0] /= trial_steps / 2;
+  ms[1] /= trial_steps / 2;
+  *total = 0.5 * (ms[0] + ms[1]);
+  advance_views(b, trial_steps + 2);
+  return LBM_OK;
+}
+
+}  // namespace
+
 lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* threads, int* blocks_per_cu,
                               double* best_ms_per_step) {
   lbm_status st = benter(b);
@@ -558,50 +632,67 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* threads, int* 
   int phase = 0;
   st = common_phase(b, &phase);
   if (st) return st;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  BHIP_TRY(b, hipEventCreate(&e0));
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return bfail(b, LBM_ERR_HIP, "hipEventCreate failed");
-  }
-  double best = 1e300;
-  int best_t = b->threads, best_b = b->blocks_per_cu;
+  std::vector<hipEvent_t> ev(trial_steps + 1, nullptr);
   lbm_status result = LBM_OK;
-  for (int t : THREAD_CHOICES) {
-    if (t < b->max_tpr) continue;
-    if ((result = build_items(b, t)) != LBM_OK) break;
-    for (int bpc : BLOCKS_PER_CU_CHOICES) {
-      b->blocks_per_cu = bpc;
-      // two untimed steps, then the timed trial; every trial has an even
-      // length, so the propagation phase is unchanged
-      launch_one(b, phase);
-      launch_one(b, phase ^ 1);
-      (void)hipEventRecord(e0, b->stream);
-      for (int s = 0; s < trial_steps; ++s) launch_one(b, phase ^ (s & 1));
-      (void)hipEventRecord(e1, b->stream);
-      if (hipEventSynchronize(e1) != hipSuccess) {
-        result = bfail(b, LBM_ERR_HIP, "autotune trial failed");
-        break;
-      }
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      advance_views(b, trial_steps + 2);
-      if (ms / trial_steps < best) {
-        best = ms / trial_steps;
-        best_t = t;
-        best_b = bpc;
-      }
+  for (hipEvent_t& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      result = bfail(b, LBM_ERR_HIP, "hipEventCreate failed");
+      break;
     }
+  // every candidate shape for both phases; per phase, the fastest launches
+  double best_step = 1e300, best_ph[2] = {1e300, 1e300};
+  int step_t = b->threads[1], step_b = b->blocks_per_cu[1];
+  int ph_t[2] = {b->threads[0], b->threads[1]};
+  int ph_b[2] = {b->blocks_per_cu[0], b->blocks_per_cu[1]};
+  for (int t : THREAD_CHOICES) {
     if (result != LBM_OK) break;
+    if (t < b->max_tpr) continue;
+    if ((result = build_items(b, t, t)) != LBM_OK) break;
+    for (int bpc : BLOCKS_PER_CU_CHOICES) {
+      b->blocks_per_cu[0] = b->blocks_per_cu[1] = bpc;
+      double ms[2], total = 0.0;
+      if ((result = time_trial(b, phase, trial_steps, ev, ms, &total)) != LBM_OK) break;
+      if (total < best_step) {
+        best_step = total;
+        step_t = t;
+        step_b = bpc;
+      }
+      for (int ph = 0; ph < 2; ++ph)
+        if (ms[ph] < best_ph[ph]) {
+          best_ph[ph] = ms[ph];
+          ph_t[ph] = t;
+          ph_b[ph] = bpc;
+        }
+    }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  // The phases' fastest shapes combined are kept only if the combination,
+  // timed as such, beats the best common shape: each phase runs on the cache
+  // state the other leaves behind.
+  int use_t[2] = {step_t, step_t}, use_b[2] = {step_b, step_b};
+  double best = best_step;
+  if (result == LBM_OK && (ph_t[0] != ph_t[1] || ph_b[0] != ph_b[1])) {
+    b->blocks_per_cu[0] = ph_b[0];
+    b->blocks_per_cu[1] = ph_b[1];
+    result = build_items(b, ph_t[0], ph_t[1]);
+    double ms[2], total = 0.0;
+    if (result == LBM_OK) result = time_trial(b, phase, trial_steps, ev, ms, &total);
+    if (result == LBM_OK && total < best_step) {
+      best = total;
+      use_t[0] = ph_t[0];
+      use_t[1] = ph_t[1];
+      use_b[0] = ph_b[0];
+      use_b[1] = ph_b[1];
+    }
+  }
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
   if (result != LBM_OK) return result;
-  b->blocks_per_cu = best_b;
-  st = build_items(b, best_t);
+  b->blocks_per_cu[0] = use_b[0];
+  b->blocks_per_cu[1] = use_b[1];
+  st = build_items(b, use_t[0], use_t[1]);
   if (st) return st;
-  if (threads) *threads = best_t;
-  if (blocks_per_cu) *blocks_per_cu = best_b;
+  if (threads) *threads = use_t[1];
+  if (blocks_per_cu) *blocks_per_cu = use_b[1];
   if (best_ms_per_step) *best_ms_per_step = best;
   return LBM_OK;
 }
@@ -611,8 +702,8 @@ lbm_status lbm_batch_get_info(const lbm_batch* b, int* count, long long* total_c
   if (!b) return LBM_ERR_ARG;
   if (count) *count = b->count;
   if (total_cells) *total_cells = b->total_cells;
-  if (threads) *threads = b->threads;
-  if (blocks_per_cu) *blocks_per_cu = b->blocks_per_cu;
+  if (threads) *threads = b->threads[1];
+  if (blocks_per_cu) *blocks_per_cu = b->blocks_per_cu[1];
   return LBM_OK;
 }
 

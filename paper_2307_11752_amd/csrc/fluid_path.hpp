@@ -119,9 +119,10 @@ __device__ __forceinline__ void fluid_cells_p0(S* __restrict__ pop, const PopInd
 // apart (px % C == 0); with PADDED, the slots x = nx .. px - 1 of each row hold
 // no cell: lanes there compute values nobody reads and send nothing along the
 // row.  L places the populations; tile: NS * px values of LDS for this row.
-// Contains block barriers: every thread of the block must call it (inactive
-// lanes with active = false).
-template <int Q, typename S, bool SHIFT, int C, bool PADDED = false>
+// NT_LOADS = false reads through the caches (for rows that share lines with
+// their neighbours, as short rows do).  Contains block barriers: every thread
+// of the block must call it (inactive lanes with active = false).
+template <int Q, typename S, bool SHIFT, int C, bool PADDED = false, bool NT_LOADS = true>
 __device__ __forceinline__ void fluid_rows_p1(S* __restrict__ pop, int nx, int px, int ny, int nz,
                                               const PopIndex& L, int row, bool active, int t, S* tile,
                                               const StepParams<typename Store<S>::T>& p) {
@@ -140,7 +141,8 @@ __device__ __forceinline__ void fluid_rows_p1(S* __restrict__ pop, int nx, int p
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const uint32_t off = L.cell((uint32_t)px * (uint32_t)(Y[1 - V::cy[i]] + ny * Z[1 - V::cz[i]]) + x0);
-      const R r = __builtin_nontemporal_load(at_byte<R>(pop + (size_t)V::opp[i] * L.pstride, off * (uint32_t)sizeof(S)));
+      const auto src = at_byte<R>(pop + (size_t)V::opp[i] * L.pstride, off * (uint32_t)sizeof(S));
+      const R r = NT_LOADS ? __builtin_nontemporal_load(src) : *src;
       if (V::cx[i] == 0)
         W::unpack(r, sv[i]);
       else

@@ -149,9 +149,18 @@ def test_batch_graph_and_launch_shapes_agree(lbm):
     """Every launch shape and graph replay gives bit-identical states."""
     fields = _fields(SHAPES, seed=5)
     results = []
-    for threads, bpc, graph in [(256, 8, 0), (128, 2, 10), (512, 16, 10), (256, 0, 4)]:
+    # (phase-0 shape, phase-1 shape, graph length)
+    for s0, s1, graph in [((256, 8), (256, 8), 0), ((128, 2), (128, 2), 10),
+                          ((512, 16), (512, 16), 10), ((256, 0), (256, 0), 4),
+                          ((512, 0), (128, 4), 6), ((128, 0), (512, 0), 0)]:
         batch = lbm.Batch(1, SHAPES, TAUS, storage="f32", shifted=True)
-        batch.set_launch(threads, bpc)
+        if s0 == s1:
+            batch.set_launch(*s0)
+        else:
+            batch.set_launch(256, 8)
+            batch.set_phase_launch(0, *s0)
+            batch.set_phase_launch(1, *s1)
+        assert (batch.phase_launch(0), batch.phase_launch(1)) == (s0, s1)
         batch.set_graph_steps(graph)
         for m, u in zip(batch, fields):
             m.init_equilibrium(None, u)
@@ -176,7 +185,9 @@ def test_batch_autotune_then_parity(orc, lbm):
     t, b, ms = batch.autotune(trial_steps=4)
     assert t in (128, 256, 512) and b in (0, 2, 4, 8, 16) and ms > 0
     info = batch.info()
-    assert (info["threads"], info["blocks_per_cu"]) == (t, b)
+    assert (info["threads"], info["blocks_per_cu"]) == (t, b) == batch.phase_launch(1)
+    t0, b0 = batch.phase_launch(0)  # each phase keeps its own fastest shape
+    assert t0 in (128, 256, 512) and b0 in (0, 2, 4, 8, 16)
     for m, u in zip(batch, fields):  # start over from the initial state
         m.init_equilibrium(None, u)
     refs = _oracles(orc, SHAPES, TAUS, fields)
@@ -212,6 +223,13 @@ def test_batch_call_order_errors(lbm):
         batch.set_launch(100, 4)
     with pytest.raises(_lib.LBMError):
         batch.set_launch(256, -1)
+    with pytest.raises(_lib.LBMError) as e:
+        batch.set_phase_launch(2, 256, 0)
+    assert e.value.status == _lib.ERR_ARG
+    with pytest.raises(_lib.LBMError):
+        batch.set_phase_launch(0, 96, 0)
+    batch.set_phase_launch(0, 512, 0)  # the other phase keeps its shape
+    assert batch.phase_launch(0) == (512, 0)
     batch.close()
 
 
