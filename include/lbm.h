@@ -267,9 +267,9 @@ lbm_status lbm_batch_get_phase_launch(const lbm_batch* b, int phase, int* thread
  * with lbm_batch_get_phase_launch).  Reports phase 1's shape in *threads /
  * *blocks_per_cu and the kept shapes' measured ms per step as
  * *best_ms_per_step (any output may be NULL).
- * Members must be initialised (any state will do); every candidate advances
- * them by trial_steps + 2 steps (the propagation phase is kept), so
- * initialise them again afterwards.  sync. */
+ * Members must be initialised (any state will do); every trial (each
+ * candidate, and the combination) advances them by trial_steps + 2 steps (the
+ * propagation phase is kept), so initialise them again afterwards.  sync. */
 lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* threads, int* blocks_per_cu,
                               double* best_ms_per_step);
 
