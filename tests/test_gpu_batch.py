@@ -23,9 +23,10 @@ def lbm():
 
 from paper_2307_11752_amd import workloads as W  # noqa: E402
 
-# Row lanes: nx = 16, 20, 64, 48 take 8-byte lanes in every storage, 18 takes
-# 4-byte lanes in 16-bit storage, odd nx one cell a lane.  (3, 3, 3): 27 cells,
-# so the last 8-byte phase-0 lane runs into the padding.  (48, 20, 18): more
+# Row lanes in phase 1: 16-bit rows take 2 cells (4 bytes) a lane, odd ones
+# stored with one padding slot (pitch nx + 1); FP32 rows 2 cells (8 bytes) a
+# lane when nx is even, else one; FP64 rows one cell a lane.  (3, 3, 3): 27
+# cells, so the last 8-byte phase-0 lane runs into the padding.  (48, 20, 18): more
 # cells than one chunk of the blocked placement for every storage type, rows
 # straddling chunks.
 SHAPES = [(5, 4, 3), (16, 9, 7), (7, 12, 5), (33, 3, 4), (3, 3, 3), (20, 17, 11), (64, 5, 2),
