@@ -620,7 +620,7 @@ def main():
         ref, csteps, cel, cfluid, cores, single = cpu_baseline(wl, args.cpu_seconds, wl.u0,
                                                                args.oracle_steps)
         cpu = {"value": round(N * csteps / cel / 1e6, 3), "unit": "MLUPS", "cores": cores,
-               "kind": "oracle",
+               "kind": "oracle", "mlups_fluid": round(cfluid * csteps / cel / 1e6, 3),
                "sample": f"{csteps} steps of the full {nx}x{ny}x{nz} lattice (FP64 oracle, "
                          f"{cel:.1f} s wall, OpenMP over z-planes)",
                "single_core": {"value": round(N / single / 1e6, 3), "unit": "MLUPS",
