@@ -686,7 +686,12 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* threads, int* 
   }
   for (hipEvent_t e : ev)
     if (e) (void)hipEventDestroy(e);
-  if (result != LBM_OK) return result;
+  if (result != LBM_OK) {
+    // trial steps may have been queued without being counted: as after a
+    // failed lbm_batch_step, the members' phases no longer describe the device
+    for (lbm_lattice* v : b->views) v->consistent = false;
+    return result;
+  }
   b->blocks_per_cu[0] = use_b[0];
   b->blocks_per_cu[1] = use_b[1];
   st = build_items(b, use_t[0], use_t[1]);
