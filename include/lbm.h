@@ -22,10 +22,11 @@
  *  * Every call returns an lbm_status (0 = LBM_OK, negative = error).  No call
  *    throws or aborts; on error the handle keeps its previous state and
  *    lbm_last_error() describes the failure.  One exception: a HIP failure
- *    inside lbm_step (lbm_batch_step) may leave some of the requested steps
- *    queued, so the lattice (every member of the batch) is then marked
- *    inconsistent: stepping and reading it return LBM_ERR_STATE until
- *    lbm_init_equilibrium or lbm_set_populations is called again.
+ *    inside lbm_step (lbm_batch_step, lbm_batch_autotune) may leave some of
+ *    the requested steps queued, so the lattice (every member of the batch)
+ *    is then marked inconsistent: stepping and reading it return
+ *    LBM_ERR_STATE until lbm_init_equilibrium or lbm_set_populations is
+ *    called again.
  *  * Cell index idx = x + nx*(y + ny*z), x fastest; N = nx*ny*nz.  D2Q9 needs nz == 1.
  *  * Device buffers are caller-owned (e.g. PyTorch tensors) and must outlive the
  *    handle.  The library never allocates device memory.
@@ -261,7 +262,8 @@ lbm_status lbm_batch_get_phase_launch(const lbm_batch* b, int phase, int* thread
 
 /* Measure every launch shape in the built-in candidate set (threads 128 /
  * 256 / 512 x blocks per CU 0 / 2 / 4 / 8 / 16) for both phases over
- * trial_steps (even) timed steps each, timing the two phases' launches apart;
+ * trial_steps (even, 2..1000) timed steps each, timing the two phases'
+ * launches apart;
  * then time each phase's fastest shape combined, and keep that combination if
  * it beats the fastest common shape, else the common shape (read the result
  * with lbm_batch_get_phase_launch).  Reports phase 1's shape in *threads /

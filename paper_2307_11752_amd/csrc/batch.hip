@@ -628,11 +628,12 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int trial_steps, int* threads, int* 
                               double* best_ms_per_step) {
   lbm_status st = benter(b);
   if (st) return st;
-  if (trial_steps < 2 || (trial_steps & 1)) return bfail(b, LBM_ERR_ARG, "trial_steps must be even and >= 2");
+  if (trial_steps < 2 || trial_steps > 1000 || (trial_steps & 1))
+    return bfail(b, LBM_ERR_ARG, "trial_steps must be even, 2..1000");
   int phase = 0;
   st = common_phase(b, &phase);
   if (st) return st;
-  std::vector<hipEvent_t> ev(trial_steps + 1, nullptr);
+  std::vector<hipEvent_t> ev(trial_steps + 1, nullptr);  // one per launch boundary
   lbm_status result = LBM_OK;
   for (hipEvent_t& e : ev)
     if (hipEventCreate(&e) != hipSuccess) {

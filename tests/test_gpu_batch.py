@@ -231,6 +231,10 @@ def test_batch_call_order_errors(lbm):
         batch.set_phase_launch(0, 96, 0)
     batch.set_phase_launch(0, 512, 0)  # the other phase keeps its shape
     assert batch.phase_launch(0) == (512, 0)
+    for bad in (0, 3, 1002):  # trial lengths must be even, 2..1000
+        with pytest.raises(_lib.LBMError) as e:
+            batch.autotune(trial_steps=bad)
+        assert e.value.status == _lib.ERR_ARG
     batch.close()
 
 
