@@ -95,10 +95,11 @@ __global__ void __launch_bounds__(512)
 // Phase 0 over every item, or phase 1 over the items of lane width lc.
 template <int Q, typename S, bool SHIFT>
 void launch_batch(const void* base, const BatchItem* items, int nitems, int phase, int lc,
-                  int grid, int threads, hipStream_t stream) {
+                  int grid, int threads, size_t lds0, hipStream_t stream) {
   constexpr int CM = Pack8<S>::C;
   if (phase == 0) {
-    hipLaunchKernelGGL((batch_step_kernel<Q, S, SHIFT, 0, CM>), dim3(grid), dim3(threads), 0,
+    // lds0: unused LDS that only caps the resident blocks per CU (0 = none)
+    hipLaunchKernelGGL((batch_step_kernel<Q, S, SHIFT, 0, CM>), dim3(grid), dim3(threads), lds0,
                        stream, (S*)base, items, nitems);
     return;
   }
@@ -114,7 +115,8 @@ void launch_batch(const void* base, const BatchItem* items, int nitems, int phas
                        stream, (S*)base, items, nitems);
 }
 
-using LaunchFn = void (*)(const void*, const BatchItem*, int, int, int, int, int, hipStream_t);
+using LaunchFn = void (*)(const void*, const BatchItem*, int, int, int, int, int, size_t,
+                           hipStream_t);
 
 template <int Q, bool SHIFT>
 LaunchFn launch_for_storage(int s) {
@@ -225,6 +227,7 @@ struct lbm_batch {
   unsigned char* aux = nullptr;
   hipStream_t stream = nullptr;
   int device = 0, num_cu = 0;
+  int lds_per_cu = 0;  // bytes of LDS per compute unit (phase-0 occupancy cap; 0 = unknown)
   BatchLayout lay;
   std::vector<lbm_lattice*> views;
   std::vector<BatchLat> lats;
@@ -328,15 +331,23 @@ void launch_one(lbm_batch* b, int phase) {
     return bpc == 0 ? std::max(1, n) : std::max(1, std::min(n, bpc * b->num_cu));
   };
   if (phase == 0) {
+    // One block per item in 128-thread blocks: at most four resident per CU,
+    // as the single lattice's phase 0 (ensemble FP32 phase 0 562 against 580
+    // us uncapped; wider blocks and FP16 measured no gain from a cap)
+    size_t lds0 = 0;
+    if (bpc == 0 && b->threads[0] == 128 && b->lds_per_cu > 0) {
+      const size_t cap = (size_t)(b->lds_per_cu / 4) & ~(size_t)1023;
+      if (cap <= 65536) lds0 = cap;
+    }
     fn(b->pop, (const BatchItem*)(b->aux + b->lay.items0_off), b->nitems0, 0, 0,
-       grid_for(b->nitems0), b->threads[0], b->stream);
+       grid_for(b->nitems0), b->threads[0], lds0, b->stream);
     return;
   }
   const BatchItem* items1 = (const BatchItem*)(b->aux + b->lay.items1_off);
   for (int k = 0; k < 3; ++k)
     if (b->lane_n[k] > 0)
       fn(b->pop, items1 + b->lane_first[k], b->lane_n[k], 1, b->lane_c[k], grid_for(b->lane_n[k]),
-         b->threads[1], b->stream);
+         b->threads[1], 0, b->stream);
 }
 
 lbm_status benter(lbm_batch* b) {
@@ -461,6 +472,11 @@ lbm_status lbm_batch_create(lbm_batch** out, lbm_descriptor d, int count, const 
   if (hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, b->device) !=
       hipSuccess)
     return undo(LBM_ERR_HIP, "hipDeviceGetAttribute failed");
+  if (hipDeviceGetAttribute(&b->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                            b->device) != hipSuccess) {
+    b->lds_per_cu = 0;        // no occupancy cap
+    (void)hipGetLastError();  // and no stale error for the next launch check
+  }
   std::vector<uint8_t> mat;
   for (int l = 0; l < count; ++l) {
     const int nx = dims[3 * l], ny = dims[3 * l + 1], nz = dims[3 * l + 2];
