@@ -186,7 +186,10 @@ template <int Q, typename S, bool SHIFT, int C>
 __global__ void __launch_bounds__(256)
     step_p0_flat_kernel(S* __restrict__ pop, uint32_t N, PopIndex L,
                         StepParams<typename Store<S>::T> p) {
-  const uint32_t c0 = (uint32_t)C * (blockIdx.x * blockDim.x + threadIdx.x);
+  // FP32 takes the blocks in descending order (TGV 256^3: phase 0 384 -> 378
+  // us, phase 1 after it unchanged; 16-bit storage loses from this order)
+  const unsigned bid = sizeof(S) == 4 ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
+  const uint32_t c0 = (uint32_t)C * (bid * blockDim.x + threadIdx.x);
   if (c0 >= N) return;
   fluid_cells_p0<Q, S, SHIFT, C>(pop, L, c0, p);
 }
