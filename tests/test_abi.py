@@ -89,6 +89,37 @@ def test_required_bytes_follows_the_documented_placement(lib):
         assert p.value == -(-nbytes // 256) * 256, (d, nx, ny, nz, st)
 
 
+
+def test_batch_required_bytes_sums_the_members(lib):
+    """A batch's population buffer is its members' buffers back to back, each
+    sized as a lattice of its own (lbm_required_bytes, a multiple of 256 bytes);
+    with 16-bit storage a member of odd nx stores its rows nx + 1 slots apart
+    (include/lbm.h, batched ensembles).  Host only."""
+    rng = np.random.default_rng(1107)
+    p, a = ctypes.c_size_t(), ctypes.c_size_t()
+    for st in (_lib.STORE_F64, _lib.STORE_F32, _lib.STORE_F16, _lib.STORE_BF16):
+        for _ in range(20):
+            count = int(rng.integers(1, 12))
+            dims = [int(v) for v in rng.integers(3, 97, 3 * count)]
+            expect = 0
+            for k in range(count):
+                nx, ny, nz = dims[3 * k: 3 * k + 3]
+                px = nx + 1 if (st in (_lib.STORE_F16, _lib.STORE_BF16) and nx % 2) else nx
+                assert lib.lbm_required_bytes(1, px, ny, nz, st, ctypes.byref(p), None) == 0
+                assert p.value % 256 == 0
+                expect += p.value
+            arr = (ctypes.c_int * len(dims))(*dims)
+            assert lib.lbm_batch_required_bytes(1, count, arr, st, ctypes.byref(p),
+                                                ctypes.byref(a)) == 0
+            assert p.value == expect, (st, dims)
+            assert a.value > 0
+    arr = (ctypes.c_int * 3)(8, 8, 8)
+    assert lib.lbm_batch_required_bytes(1, 0, arr, _lib.STORE_F32, ctypes.byref(p), None) == \
+        _lib.ERR_ARG
+    wide = (ctypes.c_int * 3)(1030, 4, 4)  # a 16-bit row of 1030 cells needs 515 lanes > 512
+    assert lib.lbm_batch_required_bytes(1, 1, wide, _lib.STORE_F16, ctypes.byref(p), None) == \
+        _lib.ERR_UNSUPPORTED
+
 def _create(lib, d=1, n=(8, 8, 8), tau=0.8, storage=1, flags=0, pop=256, pop_b=10**9, aux=512,
             aux_b=10**9):
     h = ctypes.c_void_p()
