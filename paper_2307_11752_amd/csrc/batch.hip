@@ -63,7 +63,11 @@ __global__ void __launch_bounds__(512)
   constexpr int CM = Pack8<S>::C;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   for (int it = (int)blockIdx.x; it < nitems; it += (int)gridDim.x) {
-    const BatchItem item = items[it];
+    // 16-bit phase 0 walks the items in descending order, so that it starts
+    // on the rows phase 1 wrote last (ensemble FP16 step 321.4 -> 318.7 us;
+    // FP32 and phase 1 unchanged)
+    const int itx = (PHASE == 0 && sizeof(S) == 2) ? nitems - 1 - it : it;
+    const BatchItem item = items[itx];
     const BatchItem& L = item;
     StepParams<T> p{};
     p.base = (T)Store<S>::unit;
