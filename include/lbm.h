@@ -26,7 +26,10 @@
  *    the requested steps queued, so the lattice (every member of the batch)
  *    is then marked inconsistent: stepping and reading it return
  *    LBM_ERR_STATE until lbm_init_equilibrium or lbm_set_populations is
- *    called again.
+ *    called again.  Likewise a HIP failure while a batch uploads its work
+ *    tables (lbm_batch_set_launch, lbm_batch_set_phase_launch,
+ *    lbm_batch_autotune) makes lbm_batch_step return LBM_ERR_STATE until a
+ *    launch shape is set successfully.
  *  * Cell index idx = x + nx*(y + ny*z), x fastest; N = nx*ny*nz.  D2Q9 needs nz == 1.
  *  * Device buffers are caller-owned (e.g. PyTorch tensors) and must outlive the
  *    handle.  The library never allocates device memory.

@@ -244,6 +244,9 @@ struct lbm_batch {
   // at lane_first[k] .. lane_first[k] + lane_n[k] - 1 (widest first)
   int lane_c[3] = {0, 0, 0}, lane_first[3] = {0, 0, 0}, lane_n[3] = {0, 0, 0};
   int max_tpr = 1;  // widest row in lanes: blocks need at least this many threads
+  // the device item tables match nitems0 / nitems1 / lane_*; false after a
+  // HIP failure while uploading them (stepping is refused until a rebuild)
+  bool tables_ok = false;
   int graph_steps = 0;
   hipGraphExec_t graph = nullptr;
   std::string err;
@@ -301,29 +304,37 @@ lbm_status build_items(lbm_batch* b, int t0, int t1) {
   // group the phase-1 items by lane width (one launch per width)
   std::stable_sort(i1.begin(), i1.end(),
                    [](const BatchItem& a, const BatchItem& c) { return a.c > c.c; });
+  int lane_c[3] = {0, 0, 0}, lane_first[3] = {0, 0, 0}, lane_n[3] = {0, 0, 0};
   int nk = 0;
   for (size_t k = 0; k < i1.size(); ++k) {
     if (k == 0 || i1[k].c != i1[k - 1].c) {
       if (nk == 3) return bfail(b, LBM_ERR_ARG, "more than three lane widths");  // 1, 2 and 4 only
-      b->lane_c[nk] = i1[k].c;
-      b->lane_first[nk] = (int)k;
-      b->lane_n[nk] = 0;
+      lane_c[nk] = i1[k].c;
+      lane_first[nk] = (int)k;
       ++nk;
     }
-    ++b->lane_n[nk - 1];
+    ++lane_n[nk - 1];
   }
-  for (int k = nk; k < 3; ++k) b->lane_c[k] = b->lane_first[k] = b->lane_n[k] = 0;
   if (i0.size() > b->lay.max_items0 || i1.size() > b->lay.max_items1)
     return bfail(b, LBM_ERR_ARG, "item table overflow");
+  // from here on the device tables change: the batch describes them again
+  // only once both uploads have completed
+  b->tables_ok = false;
   BHIP_TRY(b, hipMemcpyAsync(b->aux + b->lay.items0_off, i0.data(), sizeof(BatchItem) * i0.size(),
                              hipMemcpyHostToDevice, b->stream));
   BHIP_TRY(b, hipMemcpyAsync(b->aux + b->lay.items1_off, i1.data(), sizeof(BatchItem) * i1.size(),
                              hipMemcpyHostToDevice, b->stream));
   BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  for (int k = 0; k < 3; ++k) {
+    b->lane_c[k] = lane_c[k];
+    b->lane_first[k] = lane_first[k];
+    b->lane_n[k] = lane_n[k];
+  }
   b->nitems0 = (int)i0.size();
   b->nitems1 = (int)i1.size();
   b->threads[0] = t0;
   b->threads[1] = t1;
+  b->tables_ok = true;
   drop_batch_graph(b);
   return LBM_OK;
 }
@@ -540,12 +551,15 @@ lbm_status check_shape(lbm_batch* b, int threads, int blocks_per_cu) {
 }
 
 // Both phases' shapes at once; the item tables are rebuilt when a thread
-// count changes.
+// count changes (or an earlier upload failed).  On error the batch keeps its
+// previous shapes.
 lbm_status apply_shapes(lbm_batch* b, const int (&threads)[2], const int (&bpc)[2]) {
+  if (threads[0] != b->threads[0] || threads[1] != b->threads[1] || !b->tables_ok) {
+    const lbm_status st = build_items(b, threads[0], threads[1]);
+    if (st != LBM_OK) return st;
+  }
   b->blocks_per_cu[0] = bpc[0];
   b->blocks_per_cu[1] = bpc[1];
-  if (threads[0] != b->threads[0] || threads[1] != b->threads[1])
-    return build_items(b, threads[0], threads[1]);
   drop_batch_graph(b);
   return LBM_OK;
 }
@@ -582,6 +596,10 @@ lbm_status lbm_batch_step(lbm_batch* b, int n) {
   lbm_status st = benter(b);
   if (st) return st;
   if (n < 0) return bfail(b, LBM_ERR_ARG, "n must be >= 0");
+  if (!b->tables_ok)
+    return bfail(b, LBM_ERR_STATE,
+                 "a HIP failure interrupted the upload of the work-item tables: set the launch "
+                 "shape again");
   int phase = 0;
   st = common_phase(b, &phase);
   if (st) return st;
