@@ -2,8 +2,9 @@
 
 Each time step advances every member through the batch's own launches (one
 per propagation phase, and per row width class in the second); runs of steps
-are replayed from a captured HIP graph; ``autotune()`` picks the launch shape by
-measurement.  Members are lattice handles: read them with the ``Lattice``
+are replayed from a captured HIP graph; ``autotune()`` picks each phase's launch
+shape by measurement (``set_phase_launch`` / ``phase_launch`` set and read one
+phase's).  Members are lattice handles: read them with the ``Lattice``
 calls (``init_equilibrium``, ``moments``, ``totals``, ``get_populations``).
 """
 from __future__ import annotations
