@@ -86,6 +86,9 @@ def parse():
                     help="also run the FP64-storage GPU path (parity-tested against the oracle) "
                          "for this many steps and state every --variants storage's error "
                          "against it at that horizon")
+    ap.add_argument("--store-all", action="store_true",
+                    help="adjoint workload: also time the gradient with every forward state kept "
+                         "(checkpoint every step, no recomputation; ~20 GB) and compare it bitwise")
     ap.add_argument("--fd-cells", type=int, default=3,
                     help="adjoint workload: cells checked by oracle central differences")
     ap.add_argument("--fd-reference", default=None,
@@ -439,6 +442,31 @@ def bench_adjoint(args):
     alg_bytes = nfluid * ((steps + recompute) * fwd_bytes + steps * adj_bytes)
     achieved = alg_bytes / (tf + tb) / 1e9
 
+    store_all = None
+    if args.store_all:
+        # every forward state kept: no recomputation in the backward pass
+        full = A.PorousChannel(mat, 1, tau, g, steps, 1, stream=stream)
+        full.forward(d)
+        full.backward()
+        torch.cuda.synchronize()
+        sf = sb = 0.0
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            J1 = full.forward(d)
+            t1 = time.perf_counter()
+            g1 = full.backward()
+            t2 = time.perf_counter()
+            sf += t1 - t0
+            sb += t2 - t1
+        store_all = {"checkpoint_every": 1, "work_bytes": int(full.work.numel()),
+                     "gradient_ms": round((sf + sb) * 1e3 / reps, 3),
+                     "forward_ms": round(sf * 1e3 / reps, 3),
+                     "backward_ms": round(sb * 1e3 / reps, 3),
+                     "J_equal": J1 == J, "gradient_equal_bitwise": bool(torch.equal(g1, grad))}
+        full.close()
+        del full, g1
+        torch.cuda.empty_cache()
+
     cpu = None
     check = None
     if not args.no_cpu_baseline:
@@ -525,6 +553,7 @@ def bench_adjoint(args):
                      "kernel": "porous_step_kernel + porous_adjoint_kernel (whole gradient)"},
         "cpu_baseline": cpu,
         "oracle_check": check,
+        "store_all": store_all,
     }
     print(json.dumps(out), flush=True)
 

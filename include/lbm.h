@@ -302,7 +302,10 @@ const char* lbm_batch_last_error(const lbm_batch* b);
  * LBM option, Flow Control and Optimization, "Derivative Computation"),
  * reverse in time with the forward states recomputed from checkpoints taken
  * every `checkpoint_every` steps.  All device memory is one caller-owned
- * work buffer of lbm_porous_required_bytes.
+ * work buffer of lbm_porous_required_bytes: about (steps / checkpoint_every
+ * + checkpoint_every + 4) states of 76 bytes per cell.  checkpoint_every = 1
+ * keeps every forward state and recomputes none (the fastest gradient; about
+ * 20 GB for a 128 x 64 x 64 channel over 500 steps).
  * ------------------------------------------------------------------------- */
 typedef struct lbm_porous lbm_porous; /* opaque handle */
 

@@ -384,6 +384,10 @@ lbm_status pfail(lbm_porous* h, lbm_status st, const std::string& msg) {
   } while (0)
 
 float* fptr(lbm_porous* h, size_t off) { return (float*)(h->work + off); }
+// Checkpoint slot k: the state f^{k * every}.
+float* ckpt_ptr(lbm_porous* h, int k) {
+  return fptr(h, h->lay.ckpt + h->lay.state_bytes * (size_t)k);
+}
 
 // 128-thread blocks for both step kernels (measured: forward 7.9 -> 7.4 ms,
 // backward 20.3 -> 19.8 ms per gradient at 128x64x64 against 256 threads; the
@@ -510,17 +514,17 @@ lbm_status lbm_porous_forward(lbm_porous* h, const float* porosity_dev, double* 
   h->have_forward = false;
   PHIP_TRY(h, hipMemcpyAsync(h->work + h->lay.por, porosity_dev, sizeof(float) * h->N,
                              hipMemcpyDeviceToDevice, h->stream));
+  // f^t lives in checkpoint slot t / every when every divides t, else in
+  // fa / fb by the parity of t: each step writes its result where it is kept,
+  // with no copies (f^steps, never a checkpoint, ends in fa / fb)
   float* bufs[2] = {fptr(h, h->lay.fa), fptr(h, h->lay.fb)};
-  hipLaunchKernelGGL(porous_init_kernel, dim3(grid_for(h->N)), dim3(256), 0, h->stream, bufs[0],
+  auto state = [&](int t) {
+    return t % h->every == 0 && t < h->steps ? ckpt_ptr(h, t / h->every) : bufs[t & 1];
+  };
+  hipLaunchKernelGGL(porous_init_kernel, dim3(grid_for(h->N)), dim3(256), 0, h->stream, state(0),
                      (uint32_t)h->N, (uint32_t)h->PS);
-  int cur = 0;
-  for (int t = 0; t < h->steps; ++t) {
-    if (t % h->every == 0)
-      PHIP_TRY(h, hipMemcpyAsync(h->work + h->lay.ckpt + h->lay.state_bytes * (size_t)(t / h->every),
-                                 bufs[cur], h->lay.state_bytes, hipMemcpyDeviceToDevice, h->stream));
-    launch_step(h, bufs[cur], bufs[cur ^ 1]);
-    cur ^= 1;
-  }
+  for (int t = 0; t < h->steps; ++t) launch_step(h, state(t), state(t + 1));
+  const int cur = h->steps & 1;
   double* red = (double*)(h->work + h->lay.red);
   hipLaunchKernelGGL(porous_objective_kernel, dim3(1), dim3(256), 0, h->stream, bufs[cur],
                      (const uint32_t*)(h->work + h->lay.link), h->plane_x, h->nx, h->ny, h->nz,
@@ -557,13 +561,14 @@ lbm_status lbm_porous_backward(lbm_porous* h, float* grad_dev) {
   for (int k = h->lay.nckpt - 1; k >= 0; --k) {
     const int t0 = k * h->every;
     const int t1 = std::min(t0 + h->every, h->steps);
-    // recompute the segment's states f^{t0} .. f^{t1-1} from its checkpoint
+    // the segment's states: f^{t0} in its checkpoint, f^{t0+1} .. f^{t1-1}
+    // recomputed into the segment buffer (slot t - t0; slot 0 is not used)
+    float* ck = ckpt_ptr(h, k);
     float* seg = fptr(h, h->lay.seg);
-    PHIP_TRY(h, hipMemcpyAsync(seg, h->work + h->lay.ckpt + h->lay.state_bytes * (size_t)k,
-                               h->lay.state_bytes, hipMemcpyDeviceToDevice, h->stream));
-    for (int s = 1; s < t1 - t0; ++s) launch_step(h, seg + nstate * (s - 1), seg + nstate * s);
+    auto state = [&](int t) { return t == t0 ? ck : seg + nstate * (size_t)(t - t0); };
+    for (int t = t0 + 1; t < t1; ++t) launch_step(h, state(t - 1), state(t));
     for (int t = t1 - 1; t >= t0; --t) {
-      launch_adjoint(h, seg + nstate * (size_t)(t - t0), lam[cur], lam[cur ^ 1], grad_dev);
+      launch_adjoint(h, state(t), lam[cur], lam[cur ^ 1], grad_dev);
       cur ^= 1;
     }
   }
