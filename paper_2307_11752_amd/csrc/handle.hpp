@@ -31,7 +31,7 @@ inline size_t scratch_size(size_t N) {
 }
 
 struct AuxLayout {
-  size_t link, mov, result, scratch, total;
+  size_t link, mov, cls, result, scratch, total;
 };
 
 // Aux buffer of a lattice of N cells with `scratch` bytes of its own scratch
@@ -40,7 +40,8 @@ inline AuxLayout aux_layout(size_t N, size_t scratch) {
   AuxLayout a;
   a.link = 0;
   a.mov = align256(a.link + 4 * N);
-  a.result = align256(a.mov + 4 * N);
+  a.cls = align256(a.mov + 4 * N);  // one byte per cell: CELL_FLUID | CELL_MOVING
+  a.result = align256(a.cls + N);
   a.scratch = align256(a.result + sizeof(double) * RED_FIELDS);
   a.total = align256(a.scratch + scratch);
   return a;

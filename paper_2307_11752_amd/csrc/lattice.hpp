@@ -170,6 +170,10 @@ __device__ __forceinline__ void store_nt<bf16s>(bf16s* p, float v) {
 // ---------------------------------------------------------------------------
 constexpr uint32_t LINK_FLUID = 1u << 31;
 constexpr uint32_t LINK_HAS_MOVING = 1u << 30;
+// Cell classes, one byte per cell (the local phase needs no more than these
+// two bits of the link word): fluid, and has a moving-wall link.
+constexpr uint32_t CELL_FLUID = 1u;
+constexpr uint32_t CELL_MOVING = 2u;
 
 // Placement of the populations in the buffer: population i of cell c sits at
 // element i * pstride + (c >> lb) * bstride + (c & mask).

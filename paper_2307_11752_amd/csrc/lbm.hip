@@ -237,35 +237,35 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 // Masked phase 0 (lattices with walls), same lane shape as the fluid path.
 // Every lane loads its C cells' slots aligned and non-temporal together with
-// their link words (waiting for the links first would expose one memory
-// latency per wave), collides the fluid cells and writes every slot back:
-// non-fluid cells keep their values, so each line is written whole and each
-// slot still has a single writer.
+// their class bytes (waiting for the classes first would expose one memory
+// latency per wave; the local phase needs only the fluid and moving-link
+// bits, so one byte per cell instead of the 4-byte link word), collides the
+// fluid cells and writes every slot back: non-fluid cells keep their values,
+// so each line is written whole and each slot still has a single writer.
 // ---------------------------------------------------------------------------
 template <int C>
-struct LinkVec {
-  static __device__ __forceinline__ void load(const uint32_t* p, uint32_t (&lw)[C]) {
+struct ClassVec {
+  // the C cells' class bytes (CELL_FLUID | CELL_MOVING), one load per lane
+  static __device__ __forceinline__ void load(const uint8_t* p, uint32_t (&cl)[C]) {
     if constexpr (C == 1) {
-      lw[0] = __builtin_nontemporal_load(p);
+      cl[0] = __builtin_nontemporal_load(p);
     } else if constexpr (C == 2) {
-      typedef uint32_t v2 __attribute__((ext_vector_type(2)));
-      const v2 v = __builtin_nontemporal_load((const v2*)p);
-      lw[0] = v.x;
-      lw[1] = v.y;
+      const uint32_t v = __builtin_nontemporal_load((const uint16_t*)p);
+      cl[0] = v & 0xffu;
+      cl[1] = v >> 8;
     } else {
-      typedef uint32_t v4 __attribute__((ext_vector_type(4)));
-      const v4 v = __builtin_nontemporal_load((const v4*)p);
-      lw[0] = v.x;
-      lw[1] = v.y;
-      lw[2] = v.z;
-      lw[3] = v.w;
+      const uint32_t v = __builtin_nontemporal_load((const uint32_t*)p);
+      cl[0] = v & 0xffu;
+      cl[1] = (v >> 8) & 0xffu;
+      cl[2] = (v >> 16) & 0xffu;
+      cl[3] = v >> 24;
     }
   }
 };
 
 template <int Q, typename S, bool SHIFT>
 __global__ void __launch_bounds__(256)
-    step_p0_masked_kernel(S* __restrict__ pop, const uint32_t* __restrict__ link,
+    step_p0_masked_kernel(S* __restrict__ pop, const uint8_t* __restrict__ cls,
                           const uint32_t* __restrict__ mov, uint32_t N, PopIndex L,
                           StepParams<typename Store<S>::T> p) {
   using T = typename Store<S>::T;
@@ -273,10 +273,11 @@ __global__ void __launch_bounds__(256)
   constexpr int C = Pack8<S>::C;
   const uint32_t c0 = (uint32_t)C * (blockIdx.x * blockDim.x + threadIdx.x);
   if (c0 >= N) return;
-  // link words and populations are requested together: waiting for the links
-  // before issuing the population loads would expose one memory latency per wave
-  uint32_t lw[C];
-  LinkVec<C>::load(link + c0, lw);
+  // cell classes and populations are requested together: waiting for the
+  // classes before issuing the population loads would expose one memory
+  // latency per wave
+  uint32_t cl[C];
+  ClassVec<C>::load(cls + c0, cl);
   const uint32_t lo = L.cell(c0) * (uint32_t)sizeof(S);
   S sv[Q][C];
 #pragma unroll
@@ -284,8 +285,8 @@ __global__ void __launch_bounds__(256)
     Pack8<S>::unpack(__builtin_nontemporal_load(at_byte<raw8>(pop + (size_t)i * L.pstride, lo)), sv[i]);
 #pragma unroll
   for (int k = 0; k < C; ++k) {
-    if (!(lw[k] & LINK_FLUID)) continue;
-    const uint32_t mv = (p.has_moving && (lw[k] & LINK_HAS_MOVING)) ? mov[c0 + k] : 0u;
+    if (!(cl[k] & CELL_FLUID)) continue;
+    const uint32_t mv = (p.has_moving && (cl[k] & CELL_MOVING)) ? mov[c0 + k] : 0u;
     T f[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = Store<S>::cvt(sv[i][k]);
@@ -764,8 +765,8 @@ struct Ops {
       const unsigned threads = 128;
       const unsigned nb = (unsigned)((h->N / C + threads - 1) / threads);
       hipLaunchKernelGGL((step_p0_masked_kernel<Q, S, SHIFT>), dim3(nb), dim3(threads),
-                         occupancy_lds(h, sizeof(S) >= 4 ? 6 : 0, 0), h->stream, pop, link, mov, N,
-                         L, p);
+                         occupancy_lds(h, sizeof(S) >= 4 ? 6 : 0, 0), h->stream, pop,
+                         (const uint8_t*)(h->aux + h->lay.cls), mov, N, L, p);
     } else if (h->all_fluid) {  // phase 1, rows the row kernels do not take
       hipLaunchKernelGGL((step_kernel<Q, S, SHIFT, 1, false>), grid, block, 0, h->stream, pop,
                          link, mov, h->nx, h->ny, h->nz, L, h->nxb, p);
@@ -1113,6 +1114,12 @@ lbm_status lbm_set_geometry(lbm_lattice* h, const uint8_t* material, unsigned pe
   HIP_TRY(h, hipMemcpyAsync(h->aux + h->lay.link, link.data(), 4 * h->N, hipMemcpyHostToDevice,
                             h->stream));
   HIP_TRY(h, hipMemcpyAsync(h->aux + h->lay.mov, mov.data(), 4 * h->N, hipMemcpyHostToDevice,
+                            h->stream));
+  std::vector<uint8_t> cls(h->N);
+  for (size_t i = 0; i < h->N; ++i)
+    cls[i] = (uint8_t)(((link[i] & LINK_FLUID) ? CELL_FLUID : 0u) |
+                       ((link[i] & LINK_HAS_MOVING) ? CELL_MOVING : 0u));
+  HIP_TRY(h, hipMemcpyAsync(h->aux + h->lay.cls, cls.data(), h->N, hipMemcpyHostToDevice,
                             h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   drop_graph(h);
