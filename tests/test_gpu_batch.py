@@ -178,6 +178,29 @@ def test_batch_graph_and_launch_shapes_agree(lbm):
                 assert torch.equal(a, b)
 
 
+
+@pytest.mark.parametrize("storage,shifted", [("f32", False), ("f16", True)])
+def test_batch_xcd_runs_cover_every_item(lbm, storage, shifted):
+    """With one block per phase-1 item the kernel deals runs of consecutive
+    items to one XCD (a permutation of the items once there are at least
+    8 x 64 of them); the persistent shape walks them in order.  64 members of
+    16^3 in 128-thread blocks give 1024 phase-1 items: both must agree bitwise."""
+    shapes = [(16, 16, 16)] * 64
+    taus = [0.6 + 0.005 * k for k in range(64)]
+    fields = _fields(shapes, seed=17)
+    states = []
+    for bpc in (0, 16):
+        batch = lbm.Batch(1, shapes, taus, storage=storage, shifted=shifted)
+        batch.set_launch(128, bpc)
+        for m, u in zip(batch, fields):
+            m.init_equilibrium(None, u)
+        batch.step(7)
+        torch.cuda.synchronize()
+        states.append([m.get_populations() for m in batch])
+        batch.close()
+    for a, b in zip(*states):
+        assert torch.equal(a, b)
+
 def test_batch_autotune_then_parity(orc, lbm):
     fields = _fields(SHAPES, seed=9)
     batch = lbm.Batch(1, SHAPES, TAUS, storage="f64", shifted=True)
