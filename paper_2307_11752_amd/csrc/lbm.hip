@@ -86,29 +86,34 @@ __global__ void __launch_bounds__(256)
                 StepParams<typename Store<S>::T> p) {
   using T = typename Store<S>::T;
   using V = Vel<Q>;
-  // Masked phase 1 with two blocks per row (rows of 257..512 cells): blocks
-  // b and b + 8 take the two halves of one row, so that both run on one XCD
-  // (the hardware deals blocks to the 8 XCDs in turn) and the lines they
-  // share at the middle of the row are fetched into one L2 (channel step FP32
-  // 0.2148 -> 0.2119 ms, FP16 0.1258 -> 0.1243 ms).  With 16-bit storage the
+  // Masked phase 1 with two blocks per row (rows of 257..512 cells): runs of
+  // XCD_ROWS consecutive rows, both halves of each, go to one XCD (the
+  // hardware deals blocks to the 8 XCDs in turn, so blocks b, b + 8, b + 16,
+  // ... share one), so that the lines the halves share at the middle of a row
+  // are fetched into one L2 and each XCD works on one band of rows (channel
+  // step FP32 0.2148 -> 0.2047 ms, FP16 0.1258 -> 0.1202 ms; runs of 1 / 4 /
+  // 64 / 256 rows: 0.2123 / 0.2055 / 0.2129 / 0.2153 ms in FP32).  Blocks
+  // past the last whole run keep the plain order.  With 16-bit storage the
   // rows run in descending order, so that phase 1 starts on the rows phase 0
   // wrote last: that state (about 1.4 times the last-level cache for the
   // 512 x 128 x 128 channel) then partly comes from that cache (FP16 step
   // 0.1292 -> 0.1271 ms; FP32 storage, and the fully fluid row kernels, lose
   // from this order).
-  const int nrows = ny * nz;
+  constexpr int XCD_ROWS = 16;
   constexpr bool REV = MASKED && PHASE == 1 && sizeof(S) == 2;
-  int row, xb;
-  if (MASKED && PHASE == 1 && nxb == 2 && (nrows & 7) == 0) {
-    const int b = (int)blockIdx.x;
-    const int r = 8 * (b >> 4) + (b & 7);
-    xb = (b >> 3) & 1;
-    row = REV ? nrows - 1 - r : r;
-  } else {
-    const int bid = REV ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
-    row = bid / nxb;
-    xb = bid - row * nxb;
+  const int nrows = ny * nz;
+  const int b = (int)blockIdx.x;
+  int r = b / nxb;
+  int xb = b - r * nxb;
+  if (MASKED && PHASE == 1 && nxb == 2) {
+    constexpr int span = 16 * XCD_ROWS;  // blocks of one run on each of the 8 XCDs
+    if (b < (int)gridDim.x / span * span) {
+      const int k = (b >> 3) % (2 * XCD_ROWS);
+      r = XCD_ROWS * (8 * (b / span) + (b & 7)) + (k >> 1);
+      xb = k & 1;
+    }
   }
+  const int row = REV ? nrows - 1 - r : r;
   const int x = xb * (int)blockDim.x + (int)threadIdx.x;
   if (x >= nx) return;
   const int y = row % ny;
