@@ -150,13 +150,26 @@ __device__ __forceinline__ void porous_collide_cell(const float (&f)[Q], float d
   }
 }
 
+// Block order of the per-cell kernels: runs of XCD_RUN consecutive blocks
+// (rows of the lattice) go to one XCD (the hardware deals blocks to the 8
+// XCDs in turn, so blocks b, b + 8, b + 16, ... share one L2); blocks past the
+// last whole run keep the plain order.  Gradient of the 128 x 64 x 64 channel
+// 25.8 -> 25.0 ms (forward 7.02 -> 6.96, backward 18.76 -> 18.06 ms; runs of
+// 64 blocks: 25.3 ms).
+__device__ __forceinline__ uint32_t xcd_run_block() {
+  constexpr uint32_t XCD_RUN = 16, span = 8 * XCD_RUN;
+  const uint32_t b = blockIdx.x;
+  if (b >= gridDim.x / span * span) return b;
+  return XCD_RUN * (8 * (b / span) + (b & 7)) + ((b >> 3) % XCD_RUN);
+}
+
 // Forward: collide every fluid cell of src with its porosity and push to dst
 // (wall links reflect into the cell's own opposite slot).  One cell per thread.
 __global__ void __launch_bounds__(256)
     porous_step_kernel(const float* __restrict__ src, float* __restrict__ dst,
                        const float* __restrict__ por, const uint32_t* __restrict__ link, int nx,
                        int ny, int nz, uint32_t N, uint32_t PS, PorousParams p) {
-  const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t idx = xcd_run_block() * blockDim.x + threadIdx.x;
   if (idx >= N) return;
   const uint32_t lw = link[idx];
   if (!(lw & LINK_FLUID)) return;
@@ -246,7 +259,7 @@ __global__ void __launch_bounds__(256)
                           float* __restrict__ lam_cur, float* __restrict__ grad,
                           const float* __restrict__ por, const uint32_t* __restrict__ link,
                           int nx, int ny, int nz, uint32_t N, uint32_t PS, PorousParams p) {
-  const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t idx = xcd_run_block() * blockDim.x + threadIdx.x;
   if (idx >= N) return;
   const uint32_t lw = link[idx];
   if (!(lw & LINK_FLUID)) {
